@@ -1,0 +1,136 @@
+/*
+ * Plain FP64 CPU oracle of the phase-averaged bubbly-flow hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists so that the tests, the
+ * smoke check and the CPU-baseline leg of the benchmark can check the GPU
+ * path against a slow, obviously correct implementation written from the
+ * paper.  Nothing in the product path may link, load or call it.
+ *
+ * It shares no code, header, table or constant generator with the GPU
+ * library: every formula below is written again here, in the order the
+ * paper (and the readings listed in the design notes) state it.
+ *
+ * Units are SI.  State arrays are structure-of-arrays [var][z][y][x], x
+ * fastest.  Conserved slots (nvar = ndim + 3 + 2 nb):
+ *   rho, rho*u_1..ndim, E, alpha, (n R)_1..nb, (n Rdot)_1..nb
+ * (mixture conservation laws, Sec. 2 eq. euler_transport; void fraction
+ * and bin transport, Sec. 2.2 eqs. e:alpha and the bin-variable equation).
+ *
+ * Parity status per function is given in the header comment of oracle.c.
+ */
+#ifndef BUBBLY_ORACLE_H
+#define BUBBLY_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int ndim;            /* 1, 2 or 3 */
+    int n[3];            /* cells per direction, unused directions are 1 */
+    double dx[3];        /* spacing per direction (m) */
+    int bc[3][2];        /* 0 periodic, 1 reflective, per direction low/high */
+    double gamma, pi_inf, rho0, p0;   /* stiffened-gas liquid */
+    double kappa, sigma, mu, pv;      /* polytropic gas, surface tension, viscosity, vapour */
+    int nb;              /* bins (odd) */
+    double r0_median, sigma_ln;       /* lognormal equilibrium-radius distribution */
+    double cfl;
+    int split;           /* 0: sources inside RK3; 1: Strang-split adaptive bubble sub-steps */
+    double sub_rtol;     /* relative tolerance of the bubble sub-stepper */
+    int max_substeps;
+} orc_problem;
+
+/* Bins: ln(R0/R_med) on [-3 sigma, 3 sigma], composite Simpson weights of the
+ * normal pdf, normalised to sum 1 (Sec. 2.2, log-normal bins + Simpson). */
+int orc_bins(int nb, double r0_median, double sigma_ln, double *r0, double *w);
+
+/* Conserved state from primitives prim[ndim+3][N] = rho_l, u.., p_l, alpha,
+ * with every bubble at its equilibrium radius and at rest. */
+int orc_init_state(const orc_problem *pb, const double *prim, double *q);
+
+/* Per-cell diagnostics out[8][N]: n, alpha, M3, M2d, Mp, Mk, p_mix, p_l. */
+int orc_moments(const orc_problem *pb, const double *q, double *out);
+
+/* Right-hand side L(q) of the semi-discrete system (Sec. 3). */
+int orc_rhs(const orc_problem *pb, const double *q, double *rhs);
+
+/* L(q) at k listed cells only; out[k][nvar] (cell-major). */
+int orc_rhs_cells(const orc_problem *pb, const double *q, const int64_t *cells, int64_t k, double *out);
+
+/* Same as orc_rhs but with the bubble source terms left out (split mode flux part). */
+int orc_rhs_flux_only(const orc_problem *pb, const double *q, double *rhs);
+
+/* CFL time step: cfl * min over cells and directions of dx_d / (|u_d| + c). */
+double orc_cfl_dt(const orc_problem *pb, const double *q);
+
+/* One SSP-RK3 step in place.  dt <= 0 selects the CFL step.  Returns the step
+ * used in *dt_used.  With pb->split = 1 the step is Strang-split. */
+int orc_rk3_step(const orc_problem *pb, double *q, double dt, double *dt_used);
+
+/* Adaptive bubble half-step of split mode on the whole grid (exposed for tests).
+ * nsub_out (may be NULL) receives per-(cell,bin) accepted sub-step counts [nb][N]. */
+int orc_bubble_advance(const orc_problem *pb, double *q, double dt, int32_t *nsub_out);
+
+/* ---- scalar building blocks, exposed for the pins ---- */
+
+/* Keller--Miksis wall acceleration with polytropic contents (Sec. 2 eq. keller_miksis). */
+double orc_km_rddot(const orc_problem *pb, double R, double Rdot, double R0, double pg0,
+                    double p_inf, double rho, double c);
+
+/* WENO5-JS value at the right face of the centre cell from v[0..4] = cells i-2..i+2. */
+double orc_weno5(const double *v);
+
+/* HLLC flux at a face from left/right reconstructed primitive vectors
+ * W = [rho, u_1..ndim, p_l, alpha, n, B, R_1..nb, Rdot_1..nb] (length nW).
+ * dir is the face normal.  F has nvar entries in conserved-slot order. */
+int orc_hllc(const orc_problem *pb, int dir, const double *WL, const double *WR, double *F);
+
+/* Single-bubble Keller--Miksis integration with adaptive Dormand--Prince 5(4).
+ * y = (R, Rdot) at t=0.  Samples R, Rdot at the nt increasing times t_out.
+ * If r_stop > 0 the run ends when R first reaches r_stop; the crossing time is
+ * returned in *t_stop (else *t_stop = -1).  Returns the accepted step count. */
+int64_t orc_km_integrate(const orc_problem *pb, double R0, double pg0, double p_inf, double rho,
+                         double c, double R_init, double Rdot_init, double rtol, double atol_r,
+                         double atol_v, int nt, const double *t_out, double *R_out, double *V_out,
+                         double r_stop, double *t_stop);
+
+/* One Dormand--Prince 5(4) step of the single-bubble KM system from y = (R, Rdot). */
+void orc_km_dp54_step(const orc_problem *pb, double R0, double pg0, double p_inf, double rho, double c,
+                      const double *y, double h, double *y5, double *y4);
+
+/* ---- volume-averaged (Euler--Lagrange) variant, Sec. 2.1 ---- */
+
+/* Three-dimensional only.  Liquid conserved state ql[5][N] = rho_l, rho_l u,
+ * rho_l v, rho_l w, E_l (liquid-phase variables of Sec. 2.1).  Bubbles are
+ * structure-of-arrays bub[8][nbub] = x, y, z, R0, R, Rdot, pg0, h_sub, where
+ * h_sub is the last accepted sub-step (carried from one half-step to the next). */
+
+/* Truncated Gaussian regularisation kernel, eq. kernel3D. */
+double orc_el_kernel(double d, double h);
+
+/* Void fraction alpha = sum V_n delta and its material rate
+ * dalpha = sum 4 pi R_n^2 Rdot_n delta, at cell centres. */
+int orc_el_smear(const orc_problem *pb, const double *bub, int64_t nbub, double *alpha, double *dalpha);
+
+/* Kernel-weighted liquid pressure around each bubble (normalised), and the
+ * liquid density and sound speed of the host cell. */
+int orc_el_gather(const orc_problem *pb, const double *ql, const double *bub, int64_t nbub,
+                  double *p_inf, double *rho_l, double *c_l);
+
+/* Liquid right-hand side with the bubble source terms for frozen alpha, dalpha. */
+int orc_el_rhs(const orc_problem *pb, const double *ql, const double *alpha, const double *dalpha,
+               double *rhs);
+
+/* One Strang-split step: bubbles dt/2 (adaptive DP5(4)), smear, liquid SSP-RK3
+ * over dt with alpha and dalpha frozen, bubbles dt/2, smear.  dt <= 0 selects
+ * the CFL step of the liquid; the step used is returned in *dt_used.
+ * nsub_out (may be NULL) receives accepted sub-steps per bubble (both halves). */
+int orc_el_step(const orc_problem *pb, double *ql, double *bub, int64_t nbub, double dt,
+                double *alpha, double *dalpha, int32_t *nsub_out, double *dt_used);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
