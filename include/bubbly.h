@@ -1,0 +1,162 @@
+/*
+ * bubbly.h -- C ABI of libbubbly.so, the MI355X (gfx950) hot path of the
+ * phase-averaged cavitating bubbly-flow solver of Vaca-Revelo, Wilfong,
+ * Bryngelson and Gnanaskandan, "Hardware-Accelerated Phase-Averaging for
+ * Cavitating Bubbly Flows" (arXiv:2511.21031).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Every function returns int: BUB_OK (0) or a negative BUB_E* code.  No
+ *    exception crosses the ABI.  Argument errors are reported synchronously,
+ *    before anything is enqueued.
+ *  * Array arguments are caller-owned DEVICE pointers (for instance
+ *    torch.Tensor.data_ptr() of a CUDA/HIP tensor) unless marked "host".
+ *    They must stay valid until the enqueued work has finished.
+ *  * `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    work is enqueued on it; nothing synchronises the host except
+ *    bub_last_error and the functions documented as synchronous.
+ *  * Units are SI.  Fields are structure-of-arrays, [var][z][y][x] with x
+ *    fastest, N = nx*ny*nz cells per field, FP64.
+ *  * Conserved state q[nvar][N], nvar = ndim + 3 + 2*nb (Sec. 2 eq.
+ *    euler_transport, Sec. 2.2 eqs. e:alpha and the bin-variable equation):
+ *        rho, rho*u_1..ndim, E, alpha, (n R)_1..nb, (n Rdot)_1..nb
+ *    with rho the mixture density (1-alpha) rho_l, E the mixture total energy
+ *    (1-alpha)(p_l + gamma pi_inf)/(gamma-1) + rho|u|^2/2, n the bubble number
+ *    density and R, Rdot the radius and wall velocity of each equilibrium-radius
+ *    bin.  n is not stored: alpha = (4 pi/3) n mean(R^3) (eq. e:ndf) gives
+ *    n = sqrt((4 pi/3) sum_i w_i (nR_i)^3 / alpha).
+ *  * A context owns only its own small device buffers (bin table, one
+ *    primitive scratch field set, scalars for the time step and the error
+ *    word) and is not thread-safe: calls on one context must be serialised by
+ *    the caller (one stream per context is the intended use).
+ *  * Numerical failures found on the device (non-finite state, non-positive
+ *    radius, void fraction outside [0,1), p_l + pi_inf <= 0, sub-step budget
+ *    exhausted) set a sticky error word read by bub_last_error.
+ */
+#ifndef BUBBLY_H
+#define BUBBLY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    BUB_OK = 0,
+    BUB_EINVAL = -1,        /* invalid argument (null pointer, bad size, bad option) */
+    BUB_ENOMEM = -2,        /* device or host allocation failed */
+    BUB_EHIP = -3,          /* HIP runtime error (launch, copy, no device) */
+    BUB_ENONFINITE = -4,    /* device: NaN/Inf or inadmissible state (rho, alpha, p_l) */
+    BUB_ENEGR = -5,         /* device: non-positive bubble radius */
+    BUB_ESUBSTEP = -6,      /* device: adaptive bubble sub-step budget exhausted */
+    BUB_EUNSUPPORTED = -7   /* valid request this build does not support */
+};
+
+enum { BUB_BC_PERIODIC = 0, BUB_BC_REFLECTIVE = 1 };
+enum { BUB_PREC_FP64 = 0, BUB_PREC_MIXED = 1 };
+enum { BUB_BUBBLES_UNSPLIT = 0, BUB_BUBBLES_SPLIT = 1 };
+
+/* Cartesian grid.  ndim in {1,2,3}; n[d] = 1 and dx[d] ignored for d >= ndim.
+ * bc[d][0/1] = low/high boundary of direction d: periodic (both ends) or
+ * reflective (mirror ghost cells, normal velocity negated; needs n[d] >= 3). */
+typedef struct { int ndim; int n[3]; double dx[3]; int bc[3][2]; } bub_grid;
+
+/* Stiffened-gas liquid, eq. eos_liquid: p_l = (gamma-1) rho_l e_l - gamma pi_inf.
+ * rho0, p0: reference state (equilibrium bubble pressure p_g0 = p0 + 2 sigma/R0 - pv). */
+typedef struct { double gamma, pi_inf, rho0, p0; } bub_liquid;
+
+/* Bubble contents and interface: polytropic exponent kappa (p_b = p_g0 (R0/R)^(3 kappa)),
+ * surface tension sigma, liquid viscosity mu (inside Keller--Miksis only), vapour pressure pv. */
+typedef struct { double kappa, sigma, mu, pv; } bub_gas;
+
+/* Log-normal equilibrium radii (Sec. 2.2): nb odd bins over ln(R0/r0_median) in
+ * [-3 sigma_ln, 3 sigma_ln], composite Simpson weights of the normal pdf, normalised. */
+typedef struct { int nb; double r0_median, sigma_ln; } bub_bins;
+
+/* Options.  cfl: time step fraction for dt <= 0 requests.  precision:
+ * BUB_PREC_FP64 or BUB_PREC_MIXED (FP32 reconstruction/Riemann/flux differences,
+ * FP64 primitives, moments, Keller--Miksis, sources and RK accumulation).
+ * bubble_mode: BUB_BUBBLES_UNSPLIT (bubble sources inside every RK stage) or
+ * BUB_BUBBLES_SPLIT (Strang splitting with adaptive embedded RK3/RK2 bubble
+ * sub-steps, Sec. 3; sub_rtol and max_substeps apply). */
+typedef struct { double cfl; int precision; int bubble_mode; double sub_rtol; int max_substeps; } bub_opts;
+
+typedef struct bub_ctx bub_ctx;
+
+/* Create a context for one problem on the current HIP device.  Computes the bin
+ * table on the host and allocates the context's device buffers
+ * (about (ndim+6)*N*8 bytes).  *out receives the context (caller destroys it). */
+int bub_ctx_create(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas,
+                   const bub_bins *bins, const bub_opts *opts, bub_ctx **out);
+
+/* Free a context and its device buffers.  Waits for the device first. */
+int bub_ctx_destroy(bub_ctx *ctx);
+
+/* Sizes: nvar conserved variables, nprim primitive scratch fields, ncells = N,
+ * state_bytes = nvar*N*8, work_bytes = the `work` buffer bub_rk3_step needs.
+ * Any output pointer may be NULL. */
+int bub_layout(const bub_ctx *ctx, int *nvar, int *nprim, int64_t *ncells,
+               size_t *state_bytes, size_t *work_bytes);
+
+/* Copy the bin table to host arrays r0[nb], w[nb] (host pointers). */
+int bub_bins_get(const bub_ctx *ctx, double *r0, double *w);
+
+/* Conserved state from primitives (Sec. 4: initial conditions, then device
+ * residency).  prim[ndim+3][N] = rho_l, u_1..ndim, p_l, alpha (device);
+ * every bubble starts at its equilibrium radius with zero wall velocity:
+ * n = alpha / ((4 pi/3) sum w R0^3), (nR)_i = n R0_i, (nRdot)_i = 0.
+ * q[nvar][N] (device) is written. */
+int bub_init_state(bub_ctx *ctx, const double *prim, double *q, void *stream);
+
+/* Right-hand side of the semi-discrete system (Sec. 3, finite-volume form):
+ * rhs = sum_d (F_{-1/2} - F_{+1/2}) / dx_d + s, with WENO5 reconstruction
+ * (Sec. 3) of rho, u, p_l, alpha, n, B = mean(R^3 p_bw)/mean(R^3) -
+ * rho mean(R^3 Rdot^2)/mean(R^3), R_i, Rdot_i; HLLC fluxes with face pressure
+ * p = (1-alpha) p_l + alpha B (eq. e:pressure); sources 3 alpha
+ * mean(R^2 Rdot)/mean(R^3) (eq. e:alpha), n Rdot_i and n Rddot_i with Rddot_i
+ * from Keller--Miksis (eq. keller_miksis) driven by the cell's p_l.
+ * q (device, read) and rhs (device, written) are [nvar][N] and must not alias.
+ * In split mode the bubble source terms are left out (they belong to the
+ * bubble sub-steps). */
+int bub_rhs_stage(bub_ctx *ctx, const double *q, double *rhs, void *stream);
+
+/* One SSP-RK3 step (Sec. 3, third-order TVD Runge--Kutta), in place on q.
+ * work: device buffer of work_bytes (two state copies).  dt > 0: fixed step;
+ * dt <= 0: dt = cfl * min over cells and directions of dx_d/(|u_d| + c),
+ * computed on the device from q (no host synchronisation).  dt_dev (device
+ * double, may be NULL) receives the step used.  In split mode the step is
+ * S_b(dt/2) S_f(dt) S_b(dt/2) (Strang splitting, Sec. 3). */
+int bub_rk3_step(bub_ctx *ctx, double *q, double *work, double dt, double *dt_dev, void *stream);
+
+/* Per-cell diagnostics out[8][N] (device): n, alpha, M3 = mean(R^3),
+ * M2d = mean(R^2 Rdot), Mp = mean(R^3 p_bw), Mk = mean(R^3 Rdot^2), the mixture
+ * pressure of eq. e:pressure and the liquid pressure p_l.  Means are the bin
+ * quadrature sum_i w_i (.)_i. */
+int bub_moments(bub_ctx *ctx, const double *q, double *out, void *stream);
+
+/* Synchronises `stream`, then reports and clears the sticky device error word:
+ * *code (BUB_OK or a device BUB_E* code), *cell (first failing cell or -1),
+ * *bin (failing bin or -1).  Any output pointer may be NULL. */
+int bub_last_error(bub_ctx *ctx, int *code, int64_t *cell, int *bin, void *stream);
+
+/* Human-readable name of a BUB_* code (static string). */
+const char *bub_strerror(int code);
+
+/* Kernel timing for benchmarks.  bub_profile(ctx, 1) starts recording a HIP
+ * event pair around every kernel the context launches afterwards (on the
+ * stream of that call), bub_profile(ctx, 0) stops recording and discards
+ * nothing.  bub_profile_read synchronises the device, then returns the summed
+ * elapsed time in milliseconds and the launch count of one kernel kind
+ * (BUB_K_STAGE: the fused RK-stage kernel; BUB_K_PRIM: the primitive/moment
+ * pass; BUB_K_OTHER: everything else) and clears that record.  At most 65536
+ * launches are recorded between reads; later launches are not timed. */
+enum { BUB_K_STAGE = 0, BUB_K_PRIM = 1, BUB_K_OTHER = 2 };
+int bub_profile(bub_ctx *ctx, int enable);
+int bub_profile_read(bub_ctx *ctx, int kind, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BUBBLY_H */

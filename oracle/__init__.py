@@ -72,6 +72,8 @@ def lib():
         L.orc_km_integrate.argtypes = [P] + [ctypes.c_double] * 10 + [ctypes.c_int, _dp, _dp, _dp,
                                                                          ctypes.c_double, _dp]
         L.orc_km_integrate.restype = ctypes.c_int64
+        L.orc_num_threads.argtypes = []
+        L.orc_num_threads.restype = ctypes.c_int
         L.orc_el_kernel.argtypes = [ctypes.c_double, ctypes.c_double]
         L.orc_el_kernel.restype = ctypes.c_double
         L.orc_el_smear.argtypes = [P, _dp, ctypes.c_int64, _dp, _dp]
@@ -130,6 +132,10 @@ def nvar(pb) -> int:
 
 def ncells(pb) -> int:
     return pb.n[0] * pb.n[1] * pb.n[2]
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
 
 
 def bins(nb, r0_median, sigma_ln):

@@ -805,3 +805,16 @@ int64_t orc_km_integrate(const orc_problem *pb, double R0, double pg0, double pi
     }
     return steps;
 }
+
+/* Number of OpenMP threads the oracle's parallel loops use (for reporting). */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

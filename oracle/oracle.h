@@ -73,6 +73,9 @@ int orc_rk3_step(const orc_problem *pb, double *q, double dt, double *dt_used);
  * nsub_out (may be NULL) receives per-(cell,bin) accepted sub-step counts [nb][N]. */
 int orc_bubble_advance(const orc_problem *pb, double *q, double dt, int32_t *nsub_out);
 
+/* OpenMP threads used by the parallel loops (1 without OpenMP). */
+int orc_num_threads(void);
+
 /* ---- scalar building blocks, exposed for the pins ---- */
 
 /* Keller--Miksis wall acceleration with polytropic contents (Sec. 2 eq. keller_miksis). */

@@ -1,0 +1,224 @@
+"""ctypes binding of libbubbly.so: same entry points as include/bubbly.h, torch tensors in."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime that libbubbly.so then binds to (same soname)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libbubbly.so")
+
+BC_PERIODIC, BC_REFLECTIVE = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+BUBBLES_UNSPLIT, BUBBLES_SPLIT = 0, 1
+
+
+class BubblyError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        msg = _lib.bub_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} (code {code})")
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("dx", ctypes.c_double * 3),
+                ("bc", (ctypes.c_int * 2) * 3)]
+
+
+class _Liquid(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("pi_inf", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("p0", ctypes.c_double)]
+
+
+class _Gas(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_double), ("sigma", ctypes.c_double), ("mu", ctypes.c_double),
+                ("pv", ctypes.c_double)]
+
+
+class _Bins(ctypes.Structure):
+    _fields_ = [("nb", ctypes.c_int), ("r0_median", ctypes.c_double), ("sigma_ln", ctypes.c_double)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("cfl", ctypes.c_double), ("precision", ctypes.c_int), ("bubble_mode", ctypes.c_int),
+                ("sub_rtol", ctypes.c_double), ("max_substeps", ctypes.c_int)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_dp = ctypes.POINTER(ctypes.c_double)
+
+# entry point -> argtypes (all return int unless noted)
+_SIGS = {
+    "bub_ctx_create": [ctypes.POINTER(_Grid), ctypes.POINTER(_Liquid), ctypes.POINTER(_Gas),
+                       ctypes.POINTER(_Bins), ctypes.POINTER(_Opts), ctypes.POINTER(_vp)],
+    "bub_ctx_destroy": [_vp],
+    "bub_layout": [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64),
+                   ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
+    "bub_bins_get": [_vp, _dp, _dp],
+    "bub_init_state": [_vp, _vp, _vp, _vp],
+    "bub_rhs_stage": [_vp, _vp, _vp, _vp],
+    "bub_rk3_step": [_vp, _vp, _vp, ctypes.c_double, _vp, _vp],
+    "bub_moments": [_vp, _vp, _vp, _vp],
+    "bub_last_error": [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_int),
+                       _vp],
+    "bub_profile": [_vp, ctypes.c_int],
+    "bub_profile_read": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)],
+}
+
+K_STAGE, K_PRIM, K_OTHER = 0, 1, 2
+
+
+def library_path() -> str:
+    return _SO
+
+
+def lib():
+    """Load libbubbly.so (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            raise ImportError(f"{_SO} is missing: build it with `python -m paper_2511_21031_amd.build`")
+        L = ctypes.CDLL(_SO)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.bub_strerror.argtypes = [ctypes.c_int]
+        L.bub_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise BubblyError(rc, what)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _vp(stream.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 tensor on the GPU")
+    return _vp(t.data_ptr())
+
+
+class Context:
+    """One problem (grid, physics, bins, options) on the current device."""
+
+    def __init__(self, ndim, n, dx, bc, nb, r0_median=10e-6, sigma_ln=0.3, liquid=None, gas=None, cfl=0.3,
+                 precision=PREC_FP64, bubble_mode=BUBBLES_UNSPLIT, sub_rtol=1e-4, max_substeps=10000):
+        L = lib()
+        liquid = liquid or dict(gamma=7.1, pi_inf=3.06e8, rho0=1000.0, p0=101325.0)
+        gas = gas or dict(kappa=1.4, sigma=0.0728, mu=1e-3, pv=0.0)
+        g = _Grid()
+        g.ndim = ndim
+        for d in range(3):
+            g.n[d] = int(n[d]) if d < len(n) else 1
+            g.dx[d] = float(dx[d]) if d < len(dx) else 1.0
+            b = bc[d] if d < len(bc) else (0, 0)
+            g.bc[d][0], g.bc[d][1] = int(b[0]), int(b[1])
+        lq = _Liquid(liquid["gamma"], liquid["pi_inf"], liquid["rho0"], liquid["p0"])
+        gs = _Gas(gas["kappa"], gas["sigma"], gas["mu"], gas["pv"])
+        bn = _Bins(nb, r0_median, sigma_ln)
+        op = _Opts(cfl, precision, bubble_mode, sub_rtol, max_substeps)
+        h = _vp()
+        _check(L.bub_ctx_create(ctypes.byref(g), ctypes.byref(lq), ctypes.byref(gs), ctypes.byref(bn),
+                                ctypes.byref(op), ctypes.byref(h)), "bub_ctx_create")
+        self._h = h
+        self.ndim = ndim
+        self.n = tuple(g.n)
+        self.nb = nb
+        self.precision = precision
+        self.bubble_mode = bubble_mode
+        nv, npr, nc = ctypes.c_int(), ctypes.c_int(), _i64()
+        sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(L.bub_layout(h, ctypes.byref(nv), ctypes.byref(npr), ctypes.byref(nc), ctypes.byref(sb),
+                            ctypes.byref(wb)), "bub_layout")
+        self.nvar, self.nprim, self.ncells = nv.value, npr.value, nc.value
+        self.state_bytes, self.work_bytes = sb.value, wb.value
+
+    # -- lifetime -------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bub_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- helpers ----------------------------------------------------------------
+    def new_state(self, device="cuda"):
+        return torch.empty((self.nvar, self.ncells), dtype=torch.float64, device=device)
+
+    def new_work(self, device="cuda"):
+        return torch.empty((self.work_bytes // 8,), dtype=torch.float64, device=device)
+
+    def bins(self):
+        r0 = (ctypes.c_double * self.nb)()
+        w = (ctypes.c_double * self.nb)()
+        _check(lib().bub_bins_get(self._h, r0, w), "bub_bins_get")
+        return list(r0), list(w)
+
+    # -- entry points ---------------------------------------------------------------
+    def init_state(self, prim: torch.Tensor, q: torch.Tensor | None = None, stream=None):
+        if prim.shape != (self.ndim + 3, self.ncells):
+            raise ValueError(f"prim must be [{self.ndim + 3}][{self.ncells}]")
+        q = self.new_state(prim.device) if q is None else q
+        _check(lib().bub_init_state(self._h, _ptr(prim), _ptr(q), _stream(stream)), "bub_init_state")
+        return q
+
+    def rhs_stage(self, q: torch.Tensor, rhs: torch.Tensor | None = None, stream=None):
+        rhs = torch.empty_like(q) if rhs is None else rhs
+        _check(lib().bub_rhs_stage(self._h, _ptr(q), _ptr(rhs), _stream(stream)), "bub_rhs_stage")
+        return rhs
+
+    def rk3_step(self, q: torch.Tensor, work: torch.Tensor, dt: float = 0.0, dt_dev: torch.Tensor | None = None,
+                 stream=None):
+        if work.numel() * 8 < self.work_bytes:
+            raise ValueError("work buffer too small")
+        _check(lib().bub_rk3_step(self._h, _ptr(q), _ptr(work), float(dt), _ptr(dt_dev), _stream(stream)),
+               "bub_rk3_step")
+
+    def moments(self, q: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        out = torch.empty((8, self.ncells), dtype=torch.float64, device=q.device) if out is None else out
+        _check(lib().bub_moments(self._h, _ptr(q), _ptr(out), _stream(stream)), "bub_moments")
+        return out
+
+    def profile(self, enable: bool):
+        _check(lib().bub_profile(self._h, 1 if enable else 0), "bub_profile")
+
+    def profile_read(self, kind: int):
+        """(total milliseconds, launches) of one kernel kind since the last read."""
+        ms, n = ctypes.c_double(), _i64()
+        _check(lib().bub_profile_read(self._h, kind, ctypes.byref(ms), ctypes.byref(n)), "bub_profile_read")
+        return ms.value, n.value
+
+    def last_error(self, stream=None):
+        code, cell, b = ctypes.c_int(), _i64(), ctypes.c_int()
+        _check(lib().bub_last_error(self._h, ctypes.byref(code), ctypes.byref(cell), ctypes.byref(b),
+                                    _stream(stream)), "bub_last_error")
+        return code.value, cell.value, b.value
+
+
+def context_from_case(case, **kw) -> Context:
+    """Context for a ``workloads.Case`` (grid, bins, physics and CFL of the case)."""
+    return Context(case.ndim, case.n, case.dx, case.bc, case.nb, case.r0_median, case.sigma_ln, case.liquid,
+                   case.gas, case.cfl, **kw)

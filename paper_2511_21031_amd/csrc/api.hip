@@ -1,0 +1,406 @@
+// C ABI of libbubbly.so (declared in include/bubbly.h): contexts, argument
+// checks, and the launch sequences of the ensemble-averaged hot path.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <type_traits>
+
+#include "bubbly.h"
+#include "ee_kernels.hpp"
+#include "ctx.hpp"
+
+using namespace bub;
+
+#define HIP_OK(expr)                                   \
+    do {                                               \
+        if ((expr) != hipSuccess) return BUB_EHIP;     \
+    } while (0)
+
+namespace {
+
+constexpr size_t PROF_MAX = 65536;
+
+// Returns the record index to close with prof_end, or -1 when not timing.
+long prof_begin(bub_ctx *c, int kind, hipStream_t s)
+{
+    if (!c->prof_on || c->prof_used >= PROF_MAX) return -1;
+    if (c->prof_used == c->prof.size()) {
+        ProfRec r;
+        if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return -1;
+        c->prof.push_back(r);
+    }
+    ProfRec &r = c->prof[c->prof_used];
+    r.kind = kind;
+    if (hipEventRecord(r.a, s) != hipSuccess) return -1;
+    return (long)c->prof_used++;
+}
+
+void prof_end(bub_ctx *c, long idx, hipStream_t s)
+{
+    if (idx >= 0) (void)hipEventRecord(c->prof[idx].b, s);
+}
+
+// Host bin table: ln(R0/R_med) on [-3 sigma, 3 sigma], composite Simpson
+// weights of the normal pdf, normalised (Sec. 2.2: log-normal bins, Simpson's rule).
+int make_bins(int nb, double rmed, double sig, double *r0, double *w)
+{
+    if (nb < 1 || nb > NB_MAX || nb % 2 == 0 || !(rmed > 0.0)) return BUB_EINVAL;
+    if (nb == 1) {
+        r0[0] = rmed;
+        w[0] = 1.0;
+        return BUB_OK;
+    }
+    if (!(sig > 0.0)) return BUB_EINVAL;
+    const double h = 6.0 * sig / (nb - 1);
+    const double norm = 1.0 / (sig * std::sqrt(2.0 * M_PI));
+    double total = 0.0;
+    for (int i = 0; i < nb; ++i) {
+        double x = -3.0 * sig + i * h;
+        double coef = (i == 0 || i == nb - 1) ? 1.0 : (i & 1 ? 4.0 : 2.0);
+        r0[i] = rmed * std::exp(x);
+        w[i] = coef * (h / 3.0) * norm * std::exp(-0.5 * x * x / (sig * sig));
+        total += w[i];
+    }
+    for (int i = 0; i < nb; ++i) w[i] /= total;
+    return BUB_OK;
+}
+
+int blocks_for(long long n, int per = 256)
+{
+    long long b = (n + per - 1) / per;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+// Tile shape per dimensionality (LDS-staged halos; see ee_kernels.hpp).
+template <int D> struct TileCfg;
+template <> struct TileCfg<1> { static constexpr int TX = 255, TY = 1, TZ = 1, BLOCK = 256; };
+template <> struct TileCfg<2> { static constexpr int TX = 32, TY = 8, TZ = 1, BLOCK = 256; };
+template <> struct TileCfg<3> { static constexpr int TX = 8, TY = 8, TZ = 4, BLOCK = 256; };
+
+template <int D>
+int launch_prim(bub_ctx *c, const double *q, double *out, int mode, hipStream_t s)
+{
+    int nbk = blocks_for(c->g.N);
+    long pr = prof_begin(c, BUB_K_PRIM, s);
+    if (mode == PRIM_CFL)
+        hipLaunchKernelGGL((k_prim<D, PRIM_CFL>), dim3(nbk), dim3(256), 0, s, q, out, c->g, c->ph, c->bt, c->d_sc);
+    else if (mode == PRIM_MOMENTS)
+        hipLaunchKernelGGL((k_prim<D, PRIM_MOMENTS>), dim3(nbk), dim3(256), 0, s, q, out, c->g, c->ph, c->bt, c->d_sc);
+    else
+        hipLaunchKernelGGL((k_prim<D, PRIM_ONLY>), dim3(nbk), dim3(256), 0, s, q, out, c->g, c->ph, c->bt, c->d_sc);
+    prof_end(c, pr, s);
+    return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
+}
+
+template <int D>
+int launch_stage(bub_ctx *c, StageArgs A, hipStream_t s)
+{
+    using TC = TileCfg<D>;
+    using G = Geo<D, TC::TX, TC::TY, TC::TZ>;
+    A.ntile[0] = (c->g.n[0] + G::TX - 1) / G::TX;
+    A.ntile[1] = (c->g.n[1] + G::TY - 1) / G::TY;
+    A.ntile[2] = (c->g.n[2] + G::TZ - 1) / G::TZ;
+    A.ntiles = A.ntile[0] * A.ntile[1] * A.ntile[2];
+    A.nblk_per_xcd = (A.ntiles + 7) / 8;
+    long pr = prof_begin(c, BUB_K_STAGE, s);
+    hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK>), dim3(8 * A.nblk_per_xcd),
+                       dim3(TC::BLOCK), 0, s, A, c->g, c->ph, c->bt);
+    prof_end(c, pr, s);
+    return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
+}
+
+int prim(bub_ctx *c, const double *q, double *out, int mode, hipStream_t s)
+{
+    switch (c->ndim) {
+    case 1: return launch_prim<1>(c, q, out, mode, s);
+    case 2: return launch_prim<2>(c, q, out, mode, s);
+    default: return launch_prim<3>(c, q, out, mode, s);
+    }
+}
+
+int stage(bub_ctx *c, const StageArgs &A, hipStream_t s)
+{
+    switch (c->ndim) {
+    case 1: return launch_stage<1>(c, A, s);
+    case 2: return launch_stage<2>(c, A, s);
+    default: return launch_stage<3>(c, A, s);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bub_strerror(int code)
+{
+    switch (code) {
+    case BUB_OK: return "ok";
+    case BUB_EINVAL: return "invalid argument";
+    case BUB_ENOMEM: return "out of memory";
+    case BUB_EHIP: return "HIP runtime error";
+    case BUB_ENONFINITE: return "non-finite or inadmissible state";
+    case BUB_ENEGR: return "non-positive bubble radius";
+    case BUB_ESUBSTEP: return "bubble sub-step budget exhausted";
+    case BUB_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown error";
+    }
+}
+
+int bub_ctx_create(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, const bub_bins *bins,
+                   const bub_opts *opts, bub_ctx **out)
+{
+    if (!grid || !liq || !gas || !bins || !opts || !out) return BUB_EINVAL;
+    *out = nullptr;
+    if (grid->ndim < 1 || grid->ndim > 3) return BUB_EINVAL;
+    long long N = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (grid->n[d] < 1) return BUB_EINVAL;
+        if (d >= grid->ndim && grid->n[d] != 1) return BUB_EINVAL;
+        if (d < grid->ndim) {
+            if (!(grid->dx[d] > 0.0)) return BUB_EINVAL;
+            int lo = grid->bc[d][0], hi = grid->bc[d][1];
+            if ((lo != 0 && lo != 1) || lo != hi) return BUB_EINVAL;
+            if (lo == 1 && grid->n[d] < 3) return BUB_EINVAL;
+        }
+        N *= grid->n[d];
+    }
+    if (N >= (1LL << 32)) return BUB_EINVAL;
+    if (!(liq->gamma > 1.0) || !(liq->pi_inf >= 0.0) || !(liq->rho0 > 0.0) || !(liq->p0 > 0.0)) return BUB_EINVAL;
+    if (!(gas->kappa > 0.0) || !(gas->sigma >= 0.0) || !(gas->mu >= 0.0) || !(gas->pv >= 0.0)) return BUB_EINVAL;
+    if (!(opts->cfl > 0.0) || opts->cfl > 1.0) return BUB_EINVAL;
+    if (opts->precision != BUB_PREC_FP64 && opts->precision != BUB_PREC_MIXED) return BUB_EINVAL;
+    if (opts->bubble_mode != BUB_BUBBLES_UNSPLIT && opts->bubble_mode != BUB_BUBBLES_SPLIT) return BUB_EINVAL;
+    if (opts->bubble_mode == BUB_BUBBLES_SPLIT && (!(opts->sub_rtol > 0.0) || opts->max_substeps < 1))
+        return BUB_EINVAL;
+
+    bub_ctx *c = new (std::nothrow) bub_ctx();
+    if (!c) return BUB_ENOMEM;
+    c->grid = *grid;
+    c->liq = *liq;
+    c->gas = *gas;
+    c->bins = *bins;
+    c->opts = *opts;
+    int rc = make_bins(bins->nb, bins->r0_median, bins->sigma_ln, c->h_r0, c->h_w);
+    if (rc) {
+        delete c;
+        return rc;
+    }
+    c->ndim = grid->ndim;
+    c->nb = bins->nb;
+    c->nvar = c->ndim + 3 + 2 * c->nb;
+    c->nprim = c->ndim + 6;
+    c->N = N;
+    double m3 = 0.0;
+    for (int i = 0; i < c->nb; ++i) {
+        c->h_pg0[i] = liq->p0 + 2.0 * gas->sigma / c->h_r0[i] - gas->pv;
+        m3 += c->h_w[i] * c->h_r0[i] * c->h_r0[i] * c->h_r0[i];
+    }
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return BUB_EHIP;
+    }
+    size_t pbytes = sizeof(double) * (size_t)c->nprim * (size_t)N;
+    if (hipMalloc(&c->d_bins, sizeof(double) * 3 * NB_MAX) != hipSuccess ||
+        hipMalloc(&c->d_P, pbytes) != hipSuccess || hipMalloc(&c->d_sc, sizeof(Scalars)) != hipSuccess) {
+        bub_ctx_destroy(c);
+        return BUB_ENOMEM;
+    }
+    double tab[3 * NB_MAX];
+    std::memcpy(tab, c->h_r0, sizeof(double) * c->nb);
+    std::memcpy(tab + c->nb, c->h_w, sizeof(double) * c->nb);
+    std::memcpy(tab + 2 * c->nb, c->h_pg0, sizeof(double) * c->nb);
+    Scalars zero{};
+    if (hipMemcpy(c->d_bins, tab, sizeof(double) * 3 * c->nb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_sc, &zero, sizeof(Scalars), hipMemcpyHostToDevice) != hipSuccess) {
+        bub_ctx_destroy(c);
+        return BUB_EHIP;
+    }
+    c->ph.gamma = liq->gamma;
+    c->ph.pi_inf = liq->pi_inf;
+    c->ph.gm1 = liq->gamma - 1.0;
+    c->ph.inv_gm1 = 1.0 / (liq->gamma - 1.0);
+    c->ph.gpi = liq->gamma * liq->pi_inf;
+    c->ph.kappa3 = 3.0 * gas->kappa;
+    c->ph.sigma2 = 2.0 * gas->sigma;
+    c->ph.mu4 = 4.0 * gas->mu;
+    c->ph.p0 = liq->p0;
+    c->ph.rho0 = liq->rho0;
+    for (int d = 0; d < 3; ++d) {
+        c->g.n[d] = grid->n[d];
+        c->g.bc[d] = d < grid->ndim ? grid->bc[d][0] : 0;
+        c->g.inv_dx[d] = d < grid->ndim ? 1.0 / grid->dx[d] : 0.0;
+    }
+    c->g.N = N;
+    c->bt.r0 = c->d_bins;
+    c->bt.w = c->d_bins + c->nb;
+    c->bt.pg0 = c->d_bins + 2 * c->nb;
+    c->bt.nb = c->nb;
+    c->bt.m3_eq = m3;
+    *out = c;
+    return BUB_OK;
+}
+
+int bub_ctx_destroy(bub_ctx *c)
+{
+    if (!c) return BUB_EINVAL;
+    (void)hipDeviceSynchronize();
+    if (c->d_bins) (void)hipFree(c->d_bins);
+    if (c->d_P) (void)hipFree(c->d_P);
+    if (c->d_sc) (void)hipFree(c->d_sc);
+    for (ProfRec &r : c->prof) {
+        if (r.a) (void)hipEventDestroy(r.a);
+        if (r.b) (void)hipEventDestroy(r.b);
+    }
+    delete c;
+    return BUB_OK;
+}
+
+int bub_layout(const bub_ctx *c, int *nvar, int *nprim, int64_t *ncells, size_t *state_bytes, size_t *work_bytes)
+{
+    if (!c) return BUB_EINVAL;
+    size_t sb = sizeof(double) * (size_t)c->nvar * (size_t)c->N;
+    if (nvar) *nvar = c->nvar;
+    if (nprim) *nprim = c->nprim;
+    if (ncells) *ncells = c->N;
+    if (state_bytes) *state_bytes = sb;
+    if (work_bytes) *work_bytes = 2 * sb;
+    return BUB_OK;
+}
+
+int bub_bins_get(const bub_ctx *c, double *r0, double *w)
+{
+    if (!c || !r0 || !w) return BUB_EINVAL;
+    std::memcpy(r0, c->h_r0, sizeof(double) * c->nb);
+    std::memcpy(w, c->h_w, sizeof(double) * c->nb);
+    return BUB_OK;
+}
+
+int bub_init_state(bub_ctx *c, const double *prim_in, double *q, void *stream)
+{
+    if (!c || !prim_in || !q) return BUB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int nbk = blocks_for(c->N);
+    switch (c->ndim) {
+    case 1: hipLaunchKernelGGL((k_init<1>), dim3(nbk), dim3(256), 0, s, prim_in, q, c->g, c->ph, c->bt); break;
+    case 2: hipLaunchKernelGGL((k_init<2>), dim3(nbk), dim3(256), 0, s, prim_in, q, c->g, c->ph, c->bt); break;
+    default: hipLaunchKernelGGL((k_init<3>), dim3(nbk), dim3(256), 0, s, prim_in, q, c->g, c->ph, c->bt); break;
+    }
+    return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
+}
+
+int bub_moments(bub_ctx *c, const double *q, double *out, void *stream)
+{
+    if (!c || !q || !out || q == out) return BUB_EINVAL;
+    return prim(c, q, out, PRIM_MOMENTS, (hipStream_t)stream);
+}
+
+int bub_rhs_stage(bub_ctx *c, const double *q, double *rhs, void *stream)
+{
+    if (!c || !q || !rhs || q == rhs) return BUB_EINVAL;
+    if (c->opts.precision != BUB_PREC_FP64) return BUB_EUNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = prim(c, q, c->d_P, PRIM_ONLY, s);
+    if (rc) return rc;
+    StageArgs A{};
+    A.qk = q;
+    A.qn = nullptr;
+    A.qo = rhs;
+    A.P = c->d_P;
+    A.dtp = nullptr;
+    A.a = 0.0;
+    A.b = 1.0;
+    A.rhs_mode = 1;
+    A.sources = c->opts.bubble_mode == BUB_BUBBLES_UNSPLIT;
+    return stage(c, A, s);
+}
+
+int bub_rk3_step(bub_ctx *c, double *q, double *work, double dt, double *dt_dev, void *stream)
+{
+    if (!c || !q || !work) return BUB_EINVAL;
+    if (!(dt == dt) || dt == INFINITY) return BUB_EINVAL;
+    if (c->opts.precision != BUB_PREC_FP64) return BUB_EUNSUPPORTED;
+    if (c->opts.bubble_mode != BUB_BUBBLES_UNSPLIT) return BUB_EUNSUPPORTED;
+    const size_t M = (size_t)c->nvar * (size_t)c->N;
+    double *w1 = work, *w2 = work + M;
+    if ((q >= work && q < work + 2 * M) || (work >= q && work < q + M)) return BUB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const bool cfl = !(dt > 0.0);
+    int rc = prim(c, q, c->d_P, cfl ? PRIM_CFL : PRIM_ONLY, s);
+    if (rc) return rc;
+    long pr = prof_begin(c, BUB_K_OTHER, s);
+    hipLaunchKernelGGL(k_dt, dim3(1), dim3(1), 0, s, c->d_sc, cfl ? 0.0 : dt, c->opts.cfl, dt_dev);
+    prof_end(c, pr, s);
+    HIP_OK(hipGetLastError());
+    StageArgs A{};
+    A.P = c->d_P;
+    A.dtp = &c->d_sc->dt;
+    A.rhs_mode = 0;
+    A.sources = 1;
+    // stage 1: u1 = u^n + dt L(u^n)
+    A.qk = q; A.qn = nullptr; A.qo = w1; A.a = 0.0; A.b = 1.0;
+    if ((rc = stage(c, A, s))) return rc;
+    // stage 2: u2 = 3/4 u^n + 1/4 (u1 + dt L(u1))
+    if ((rc = prim(c, w1, c->d_P, PRIM_ONLY, s))) return rc;
+    A.qk = w1; A.qn = q; A.qo = w2; A.a = 0.75; A.b = 0.25;
+    if ((rc = stage(c, A, s))) return rc;
+    // stage 3: u^{n+1} = 1/3 u^n + 2/3 (u2 + dt L(u2)), written over u^n (own-cell reads only)
+    if ((rc = prim(c, w2, c->d_P, PRIM_ONLY, s))) return rc;
+    A.qk = w2; A.qn = q; A.qo = q; A.a = 1.0 / 3.0; A.b = 2.0 / 3.0;
+    return stage(c, A, s);
+}
+
+int bub_last_error(bub_ctx *c, int *code, int64_t *cell, int *bin, void *stream)
+{
+    if (!c) return BUB_EINVAL;
+    HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    Scalars h{};
+    HIP_OK(hipMemcpy(&h, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost));
+    if (code) *code = h.err_code;
+    if (cell) *cell = h.err_code ? h.err_cell : -1;
+    if (bin) *bin = h.err_code ? h.err_bin : -1;
+    Scalars cleared = h;
+    cleared.err_code = 0;
+    cleared.err_bin = 0;
+    cleared.err_cell = 0;
+    HIP_OK(hipMemcpy(c->d_sc, &cleared, sizeof(Scalars), hipMemcpyHostToDevice));
+    return BUB_OK;
+}
+
+int bub_profile(bub_ctx *c, int enable)
+{
+    if (!c) return BUB_EINVAL;
+    c->prof_on = enable ? 1 : 0;
+    return BUB_OK;
+}
+
+int bub_profile_read(bub_ctx *c, int kind, double *total_ms, int64_t *launches)
+{
+    if (!c || kind < BUB_K_STAGE || kind > BUB_K_OTHER) return BUB_EINVAL;
+    HIP_OK(hipDeviceSynchronize());
+    double tot = 0.0;
+    int64_t cnt = 0;
+    size_t keep = 0;
+    for (size_t i = 0; i < c->prof_used; ++i) {
+        ProfRec &r = c->prof[i];
+        if (r.kind == kind) {
+            float ms = 0.0f;
+            HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+            tot += ms;
+            ++cnt;
+        } else {
+            std::swap(c->prof[keep++], r);
+        }
+    }
+    c->prof_used = keep;
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = cnt;
+    return BUB_OK;
+}
+
+}  // extern "C"

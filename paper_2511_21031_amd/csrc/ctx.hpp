@@ -1,0 +1,35 @@
+// Context of one problem: host copies of the inputs, the bin table, and the
+// context-owned device buffers (bin table, primitive scratch, scalars).
+#pragma once
+
+#include <vector>
+
+#include "bubbly.h"
+#include "device_common.hpp"
+
+// One timed launch: events recorded on the launch stream around the kernel.
+struct ProfRec {
+    hipEvent_t a = nullptr, b = nullptr;
+    int kind = 0;
+};
+
+struct bub_ctx {
+    int device = 0;
+    bub_grid grid{};
+    bub_liquid liq{};
+    bub_gas gas{};
+    bub_bins bins{};
+    bub_opts opts{};
+    int ndim = 0, nb = 0, nvar = 0, nprim = 0;
+    long long N = 0;
+    double h_r0[bub::NB_MAX]{}, h_w[bub::NB_MAX]{}, h_pg0[bub::NB_MAX]{};
+    double *d_bins = nullptr;    // [3][nb]: r0, w, pg0
+    double *d_P = nullptr;       // [nprim][N] primitive scratch
+    bub::Scalars *d_sc = nullptr;
+    bub::Phys ph{};
+    bub::Grid g{};
+    bub::Bins bt{};
+    int prof_on = 0;
+    size_t prof_used = 0;
+    std::vector<ProfRec> prof;
+};

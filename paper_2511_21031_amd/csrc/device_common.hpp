@@ -1,0 +1,138 @@
+// Device building blocks of the ensemble-averaged RHS stage (gfx950).
+//
+// Every formula here follows the paper: stiffened-gas liquid (eq. eos_liquid),
+// mixture pressure (eq. e:pressure), Keller--Miksis with polytropic contents
+// (eq. keller_miksis), WENO5 reconstruction and HLLC fluxes (Sec. 3).  The
+// arithmetic is arranged for the GPU (one reciprocal per WENO weight set,
+// products instead of divisions where the value is unchanged), so results
+// agree with a plain evaluation to rounding, not bit for bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bub {
+
+constexpr int NB_MAX = 63;
+constexpr double FOUR_PI_3 = 4.18879020478639098461685784437;  // 4 pi / 3
+
+// Physical constants, passed by value (kernel argument segment -> SGPRs).
+struct Phys {
+    double gamma, pi_inf, gm1, inv_gm1, gpi;  // gpi = gamma * pi_inf
+    double kappa3, sigma2, mu4;               // 3 kappa, 2 sigma, 4 mu
+    double p0, rho0;
+};
+
+// Grid: cells per direction, boundary kind per direction (0 periodic,
+// 1 reflective; both ends equal), inverse spacing.
+struct Grid {
+    int n[3];
+    int bc[3];
+    double inv_dx[3];
+    long long N;
+};
+
+// Bin table in device memory: r0[nb], w[nb], pg0[nb].
+struct Bins {
+    const double *r0, *w, *pg0;
+    int nb;
+    double m3_eq;  // sum w r0^3
+};
+
+// Device scalars of one context.
+struct Scalars {
+    unsigned long long wmax;  // bit pattern of max (|u_d| + c)/dx_d (positive double)
+    double dt;                // step used by the last rk3_step
+    int err_code;             // sticky first error (0 = none)
+    int err_bin;
+    long long err_cell;
+};
+
+enum { E_NONFINITE = -4, E_NEGR = -5, E_SUBSTEP = -6 };
+
+__device__ inline void raise_error(Scalars *s, int code, long long cell, int bin)
+{
+    if (atomicCAS(&s->err_code, 0, code) == 0) {
+        s->err_cell = cell;
+        s->err_bin = bin;
+    }
+}
+
+// Ghost-cell map of one coordinate.  Periodic: wrap.  Reflective: fold with
+// period 2n (one mirror per wall crossing); `flip` toggles on every mirror so
+// the normal velocity of the ghost is negated.
+__host__ __device__ inline int map_coord(int i, int n, int bc, bool &flip)
+{
+    if ((unsigned)i < (unsigned)n) return i;
+    if (bc == 0) {
+        int m = i % n;
+        return m < 0 ? m + n : m;
+    }
+    int p = 2 * n;
+    int m = i % p;
+    if (m < 0) m += p;
+    if (m >= n) {
+        m = p - 1 - m;
+        flip = !flip;
+    }
+    return m;
+}
+
+// WENO5-JS face value at the right face of v2 from v0..v4 (cells i-2..i+2).
+// The three nonlinear weights d_k/(eps+beta_k)^2 are formed as products over
+// the other two indicators so one division normalises them (FP64 range holds).
+template <typename T>
+__device__ inline T weno5(T v0, T v1, T v2, T v3, T v4)
+{
+    const T eps = T(1e-16);
+    const T c16 = T(1.0 / 6.0);
+    const T c1312 = T(13.0 / 12.0);
+    T q0 = (T(2) * v0 - T(7) * v1 + T(11) * v2) * c16;
+    T q1 = (-v1 + T(5) * v2 + T(2) * v3) * c16;
+    T q2 = (T(2) * v2 + T(5) * v3 - v4) * c16;
+    T d0 = v0 - T(2) * v1 + v2, e0 = v0 - T(4) * v1 + T(3) * v2;
+    T d1 = v1 - T(2) * v2 + v3, e1 = v1 - v3;
+    T d2 = v2 - T(2) * v3 + v4, e2 = T(3) * v2 - T(4) * v3 + v4;
+    T b0 = c1312 * d0 * d0 + T(0.25) * e0 * e0;
+    T b1 = c1312 * d1 * d1 + T(0.25) * e1 * e1;
+    T b2 = c1312 * d2 * d2 + T(0.25) * e2 * e2;
+    T s0 = (eps + b0) * (eps + b0);
+    T s1 = (eps + b1) * (eps + b1);
+    T s2 = (eps + b2) * (eps + b2);
+    T a0 = T(0.1) * (s1 * s2);
+    T a1 = T(0.6) * (s0 * s2);
+    T a2 = T(0.3) * (s0 * s1);
+    return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+}
+
+// Keller--Miksis wall acceleration (eq. keller_miksis) with polytropic
+// contents; the R-ddot part of d(p_bw)/dt that comes from the viscous term is
+// moved to the left-hand side (exact rearrangement).
+__device__ inline double km_rddot(const Phys &ph, double R, double V, double r0, double pg0,
+                                  double pinf, double rho, double c)
+{
+    double iR = 1.0 / R;
+    double pb = pg0 * exp2(ph.kappa3 * log2(r0 * iR));
+    double pbw = pb - ph.mu4 * V * iR - ph.sigma2 * iR;
+    double dpbw = (-ph.kappa3 * pb * V + ph.mu4 * V * V * iR + ph.sigma2 * V * iR) * iR;
+    double irc = 1.0 / (rho * c);
+    double ic = 1.0 / c;
+    double num = (1.0 + V * ic) * (pbw - pinf) / rho + R * dpbw * irc - 1.5 * V * V * (1.0 - V * ic * (1.0 / 3.0));
+    double den = R * (1.0 - V * ic) + ph.mu4 * irc;
+    return num / den;
+}
+
+// Bubble-wall pressure p_bw = p_b - 4 mu Rdot/R - 2 sigma/R.
+__device__ inline double p_wall(const Phys &ph, double R, double V, double r0, double pg0)
+{
+    double iR = 1.0 / R;
+    double pb = pg0 * exp2(ph.kappa3 * log2(r0 * iR));
+    return pb - ph.mu4 * V * iR - ph.sigma2 * iR;
+}
+
+template <typename T>
+__device__ inline T dmin(T a, T b) { return a < b ? a : b; }
+template <typename T>
+__device__ inline T dmax(T a, T b) { return a > b ? a : b; }
+
+}  // namespace bub
