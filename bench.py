@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -88,11 +90,18 @@ def main():
     from paper_2511_21031_amd._binding import K_STAGE, K_PRIM, K_OTHER
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB read, 1 GiB written
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     case = workloads.c2()
     prec = bub.PREC_FP64 if args.precision == "fp64" else bub.PREC_MIXED
     ctx = bub.context_from_case(case, precision=prec)
     q = ctx.init_state(torch.from_numpy(case.prim).cuda())
     work = ctx.new_work()
+    best, tile_ms = ctx.autotune(q, reps=5)     # project autotuner: fastest stage-kernel tile on this state
     for _ in range(args.warmup):
         ctx.rk3_step(q, work)
     torch.cuda.synchronize()
@@ -137,7 +146,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "2D 1024x1024 periodic ensemble-averaged, 31 log-normal bins (sigma 0.5), "
                                "1 atm plane sine wave, CFL 0.3",
-                   "cells": N, "bins": nb, "nvar": nvar, "precision": args.precision},
+                   "cells": N, "bins": nb, "nvar": nvar, "precision": args.precision,
+                   "tile": list(ctx.tiles()[best]), "autotune_ms": [round(m, 4) for m in tile_ms]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "kernels": {"k_stage_avg_ms": stage_ms / max(stage_n, 1), "k_stage_launches": stage_n,

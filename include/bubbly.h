@@ -144,6 +144,26 @@ int bub_last_error(bub_ctx *ctx, int *code, int64_t *cell, int *bin, void *strea
 /* Human-readable name of a BUB_* code (static string). */
 const char *bub_strerror(int code);
 
+/* Tile shapes of the fused stage kernel.  Each dimensionality has a fixed list
+ * of compiled shapes (tile extent tx*ty*tz cells, `block` threads); a context
+ * starts on shape 0.  Results do not depend on the shape (each face flux is
+ * computed by the same arithmetic whichever tile owns it); only speed does.
+ * bub_tile_info: shape idx of this context's dimensionality (host outputs).
+ * bub_tile_set / bub_tile_get: select / query the shape used by later calls. */
+int bub_tile_count(const bub_ctx *ctx, int *count);
+int bub_tile_info(const bub_ctx *ctx, int idx, int *tx, int *ty, int *tz, int *block);
+int bub_tile_set(bub_ctx *ctx, int idx);
+int bub_tile_get(const bub_ctx *ctx, int *idx);
+
+/* Autotuner: times `reps` launches of the fused stage kernel (right-hand-side
+ * form) for every tile shape on the caller's state q (device, read) with
+ * `scratch` (device, state_bytes, overwritten) as output, selects the fastest
+ * for this context and returns it in *best (may be NULL).  ms_out (host,
+ * bub_tile_count entries, may be NULL) receives the mean time per launch of
+ * each shape.  Synchronises `stream`. */
+int bub_autotune(bub_ctx *ctx, const double *q, double *scratch, int reps, double *ms_out, int *best,
+                 void *stream);
+
 /* Kernel timing for benchmarks.  bub_profile(ctx, 1) starts recording a HIP
  * event pair around every kernel the context launches afterwards (on the
  * stream of that call), bub_profile(ctx, 0) stops recording and discards

@@ -64,6 +64,11 @@ _SIGS = {
     "bub_moments": [_vp, _vp, _vp, _vp],
     "bub_last_error": [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_int),
                        _vp],
+    "bub_tile_count": [_vp, ctypes.POINTER(ctypes.c_int)],
+    "bub_tile_info": [_vp, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4,
+    "bub_tile_set": [_vp, ctypes.c_int],
+    "bub_tile_get": [_vp, ctypes.POINTER(ctypes.c_int)],
+    "bub_autotune": [_vp, _vp, _vp, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int), _vp],
     "bub_profile": [_vp, ctypes.c_int],
     "bub_profile_read": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)],
 }
@@ -201,6 +206,37 @@ class Context:
         out = torch.empty((8, self.ncells), dtype=torch.float64, device=q.device) if out is None else out
         _check(lib().bub_moments(self._h, _ptr(q), _ptr(out), _stream(stream)), "bub_moments")
         return out
+
+    def tiles(self):
+        """List of (tx, ty, tz, block) stage-kernel tile shapes for this dimensionality."""
+        n = ctypes.c_int()
+        _check(lib().bub_tile_count(self._h, ctypes.byref(n)), "bub_tile_count")
+        out = []
+        for i in range(n.value):
+            v = [ctypes.c_int() for _ in range(4)]
+            _check(lib().bub_tile_info(self._h, i, *[ctypes.byref(x) for x in v]), "bub_tile_info")
+            out.append(tuple(x.value for x in v))
+        return out
+
+    @property
+    def tile(self) -> int:
+        v = ctypes.c_int()
+        _check(lib().bub_tile_get(self._h, ctypes.byref(v)), "bub_tile_get")
+        return v.value
+
+    @tile.setter
+    def tile(self, idx: int):
+        _check(lib().bub_tile_set(self._h, int(idx)), "bub_tile_set")
+
+    def autotune(self, q: torch.Tensor, scratch: torch.Tensor | None = None, reps: int = 5, stream=None):
+        """Time every tile shape on q, keep the fastest; returns (best index, ms per launch per shape)."""
+        scratch = torch.empty_like(q) if scratch is None else scratch
+        n = len(self.tiles())
+        ms = (ctypes.c_double * n)()
+        best = ctypes.c_int()
+        _check(lib().bub_autotune(self._h, _ptr(q), _ptr(scratch), int(reps), ms, ctypes.byref(best),
+                                  _stream(stream)), "bub_autotune")
+        return best.value, list(ms)
 
     def profile(self, enable: bool):
         _check(lib().bub_profile(self._h, 1 if enable else 0), "bub_profile")

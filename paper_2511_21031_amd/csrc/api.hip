@@ -77,11 +77,29 @@ int blocks_for(long long n, int per = 256)
     return (int)b;
 }
 
-// Tile shape per dimensionality (LDS-staged halos; see ee_kernels.hpp).
-template <int D> struct TileCfg;
-template <> struct TileCfg<1> { static constexpr int TX = 255, TY = 1, TZ = 1, BLOCK = 256; };
-template <> struct TileCfg<2> { static constexpr int TX = 32, TY = 8, TZ = 1, BLOCK = 256; };
-template <> struct TileCfg<3> { static constexpr int TX = 8, TY = 8, TZ = 4, BLOCK = 256; };
+// Tile shapes of the stage kernel per dimensionality: (TX, TY, TZ, BLOCK).
+// Shape 0 is the default; the autotuner may pick another per context.
+template <int D, int V> struct Tile;
+template <> struct Tile<1, 0> { static constexpr int TX = 255, TY = 1, TZ = 1, BLOCK = 256; };
+template <> struct Tile<1, 1> { static constexpr int TX = 127, TY = 1, TZ = 1, BLOCK = 128; };
+template <> struct Tile<1, 2> { static constexpr int TX = 511, TY = 1, TZ = 1, BLOCK = 512; };
+template <> struct Tile<2, 0> { static constexpr int TX = 32, TY = 8, TZ = 1, BLOCK = 256; };
+template <> struct Tile<2, 1> { static constexpr int TX = 31, TY = 8, TZ = 1, BLOCK = 256; };
+template <> struct Tile<2, 2> { static constexpr int TX = 64, TY = 4, TZ = 1, BLOCK = 256; };
+template <> struct Tile<2, 3> { static constexpr int TX = 32, TY = 16, TZ = 1, BLOCK = 512; };
+template <> struct Tile<3, 0> { static constexpr int TX = 8, TY = 8, TZ = 4, BLOCK = 256; };
+template <> struct Tile<3, 1> { static constexpr int TX = 16, TY = 4, TZ = 4, BLOCK = 256; };
+template <> struct Tile<3, 2> { static constexpr int TX = 8, TY = 4, TZ = 4, BLOCK = 128; };
+constexpr int TILE_COUNT[4] = {0, 3, 4, 3};
+
+template <int D, int V>
+void tile_info(int *tx, int *ty, int *tz, int *block)
+{
+    *tx = Tile<D, V>::TX;
+    *ty = Tile<D, V>::TY;
+    *tz = Tile<D, V>::TZ;
+    *block = Tile<D, V>::BLOCK;
+}
 
 template <int D>
 int launch_prim(bub_ctx *c, const double *q, double *out, int mode, hipStream_t s)
@@ -98,10 +116,10 @@ int launch_prim(bub_ctx *c, const double *q, double *out, int mode, hipStream_t 
     return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
 }
 
-template <int D>
-int launch_stage(bub_ctx *c, StageArgs A, hipStream_t s)
+template <int D, int V>
+int launch_stage_v(bub_ctx *c, StageArgs A, hipStream_t s)
 {
-    using TC = TileCfg<D>;
+    using TC = Tile<D, V>;
     using G = Geo<D, TC::TX, TC::TY, TC::TZ>;
     A.ntile[0] = (c->g.n[0] + G::TX - 1) / G::TX;
     A.ntile[1] = (c->g.n[1] + G::TY - 1) / G::TY;
@@ -126,10 +144,21 @@ int prim(bub_ctx *c, const double *q, double *out, int mode, hipStream_t s)
 
 int stage(bub_ctx *c, const StageArgs &A, hipStream_t s)
 {
+    const int v = c->tile;
     switch (c->ndim) {
-    case 1: return launch_stage<1>(c, A, s);
-    case 2: return launch_stage<2>(c, A, s);
-    default: return launch_stage<3>(c, A, s);
+    case 1:
+        if (v == 1) return launch_stage_v<1, 1>(c, A, s);
+        if (v == 2) return launch_stage_v<1, 2>(c, A, s);
+        return launch_stage_v<1, 0>(c, A, s);
+    case 2:
+        if (v == 1) return launch_stage_v<2, 1>(c, A, s);
+        if (v == 2) return launch_stage_v<2, 2>(c, A, s);
+        if (v == 3) return launch_stage_v<2, 3>(c, A, s);
+        return launch_stage_v<2, 0>(c, A, s);
+    default:
+        if (v == 1) return launch_stage_v<3, 1>(c, A, s);
+        if (v == 2) return launch_stage_v<3, 2>(c, A, s);
+        return launch_stage_v<3, 0>(c, A, s);
     }
 }
 
@@ -370,6 +399,93 @@ int bub_last_error(bub_ctx *c, int *code, int64_t *cell, int *bin, void *stream)
     cleared.err_cell = 0;
     HIP_OK(hipMemcpy(c->d_sc, &cleared, sizeof(Scalars), hipMemcpyHostToDevice));
     return BUB_OK;
+}
+
+int bub_tile_count(const bub_ctx *c, int *count)
+{
+    if (!c || !count) return BUB_EINVAL;
+    *count = TILE_COUNT[c->ndim];
+    return BUB_OK;
+}
+
+int bub_tile_info(const bub_ctx *c, int idx, int *tx, int *ty, int *tz, int *block)
+{
+    if (!c || !tx || !ty || !tz || !block || idx < 0 || idx >= TILE_COUNT[c->ndim]) return BUB_EINVAL;
+    switch (c->ndim * 10 + idx) {
+    case 10: tile_info<1, 0>(tx, ty, tz, block); break;
+    case 11: tile_info<1, 1>(tx, ty, tz, block); break;
+    case 12: tile_info<1, 2>(tx, ty, tz, block); break;
+    case 20: tile_info<2, 0>(tx, ty, tz, block); break;
+    case 21: tile_info<2, 1>(tx, ty, tz, block); break;
+    case 22: tile_info<2, 2>(tx, ty, tz, block); break;
+    case 23: tile_info<2, 3>(tx, ty, tz, block); break;
+    case 30: tile_info<3, 0>(tx, ty, tz, block); break;
+    case 31: tile_info<3, 1>(tx, ty, tz, block); break;
+    default: tile_info<3, 2>(tx, ty, tz, block); break;
+    }
+    return BUB_OK;
+}
+
+int bub_tile_set(bub_ctx *c, int idx)
+{
+    if (!c || idx < 0 || idx >= TILE_COUNT[c->ndim]) return BUB_EINVAL;
+    c->tile = idx;
+    return BUB_OK;
+}
+
+int bub_tile_get(const bub_ctx *c, int *idx)
+{
+    if (!c || !idx) return BUB_EINVAL;
+    *idx = c->tile;
+    return BUB_OK;
+}
+
+int bub_autotune(bub_ctx *c, const double *q, double *scratch, int reps, double *ms_out, int *best, void *stream)
+{
+    if (!c || !q || !scratch || q == scratch || reps < 1) return BUB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = prim(c, q, c->d_P, PRIM_ONLY, s);
+    if (rc) return rc;
+    StageArgs A{};
+    A.qk = q;
+    A.qo = scratch;
+    A.P = c->d_P;
+    A.b = 1.0;
+    A.rhs_mode = 1;
+    A.sources = c->opts.bubble_mode == BUB_BUBBLES_UNSPLIT;
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    const int keep = c->tile, prof = c->prof_on;
+    c->prof_on = 0;
+    double best_ms = 1e300;
+    int best_v = keep;
+    for (int v = 0; v < TILE_COUNT[c->ndim] && rc == BUB_OK; ++v) {
+        c->tile = v;
+        rc = stage(c, A, s);  // warm-up (code load)
+        if (rc) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = BUB_EHIP; break; }
+        for (int r = 0; r < reps && rc == BUB_OK; ++r) rc = stage(c, A, s);
+        if (rc) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = BUB_EHIP;
+            break;
+        }
+        double per = ms / reps;
+        if (ms_out) ms_out[v] = per;
+        if (per < best_ms) {
+            best_ms = per;
+            best_v = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->prof_on = prof;
+    c->tile = rc == BUB_OK ? best_v : keep;
+    if (best) *best = c->tile;
+    return rc;
 }
 
 int bub_profile(bub_ctx *c, int enable)

@@ -78,11 +78,46 @@ __host__ __device__ inline int map_coord(int i, int n, int bc, bool &flip)
     return m;
 }
 
+// 1/x to full FP64 precision: hardware reciprocal estimate refined by two
+// Newton steps (x finite and nonzero).  Cheaper than an IEEE division; agrees
+// with 1/x to about one ulp.
+__device__ inline double frcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
+}
+
 // WENO5-JS face value at the right face of v2 from v0..v4 (cells i-2..i+2).
 // The three nonlinear weights d_k/(eps+beta_k)^2 are formed as products over
-// the other two indicators so one division normalises them (FP64 range holds).
+// the other two indicators so one reciprocal normalises them (FP64 range holds).
+__device__ inline double weno5(double v0, double v1, double v2, double v3, double v4)
+{
+    const double eps = 1e-16;
+    const double c16 = 1.0 / 6.0;
+    const double c1312 = 13.0 / 12.0;
+    double q0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) * c16;
+    double q1 = (-v1 + 5.0 * v2 + 2.0 * v3) * c16;
+    double q2 = (2.0 * v2 + 5.0 * v3 - v4) * c16;
+    double d0 = v0 - 2.0 * v1 + v2, e0 = v0 - 4.0 * v1 + 3.0 * v2;
+    double d1 = v1 - 2.0 * v2 + v3, e1 = v1 - v3;
+    double d2 = v2 - 2.0 * v3 + v4, e2 = 3.0 * v2 - 4.0 * v3 + v4;
+    double s0 = eps + (c1312 * d0 * d0 + 0.25 * e0 * e0);
+    double s1 = eps + (c1312 * d1 * d1 + 0.25 * e1 * e1);
+    double s2 = eps + (c1312 * d2 * d2 + 0.25 * e2 * e2);
+    s0 *= s0;
+    s1 *= s1;
+    s2 *= s2;
+    double a0 = 0.1 * (s1 * s2);
+    double a1 = 0.6 * (s0 * s2);
+    double a2 = 0.3 * (s0 * s1);
+    return (a0 * q0 + a1 * q1 + a2 * q2) * frcp(a0 + a1 + a2);
+}
+
+// Generic-precision variant (used by the mixed form).
 template <typename T>
-__device__ inline T weno5(T v0, T v1, T v2, T v3, T v4)
+__device__ inline T weno5_t(T v0, T v1, T v2, T v3, T v4)
 {
     const T eps = T(1e-16);
     const T c16 = T(1.0 / 6.0);
@@ -108,24 +143,24 @@ __device__ inline T weno5(T v0, T v1, T v2, T v3, T v4)
 // Keller--Miksis wall acceleration (eq. keller_miksis) with polytropic
 // contents; the R-ddot part of d(p_bw)/dt that comes from the viscous term is
 // moved to the left-hand side (exact rearrangement).
+// irho = 1/rho and ic = 1/c of the driving liquid are passed in (shared by all bins of a cell).
 __device__ inline double km_rddot(const Phys &ph, double R, double V, double r0, double pg0,
-                                  double pinf, double rho, double c)
+                                  double pinf, double irho, double ic)
 {
-    double iR = 1.0 / R;
+    double iR = frcp(R);
     double pb = pg0 * exp2(ph.kappa3 * log2(r0 * iR));
     double pbw = pb - ph.mu4 * V * iR - ph.sigma2 * iR;
     double dpbw = (-ph.kappa3 * pb * V + ph.mu4 * V * V * iR + ph.sigma2 * V * iR) * iR;
-    double irc = 1.0 / (rho * c);
-    double ic = 1.0 / c;
-    double num = (1.0 + V * ic) * (pbw - pinf) / rho + R * dpbw * irc - 1.5 * V * V * (1.0 - V * ic * (1.0 / 3.0));
+    double irc = irho * ic;
+    double num = (1.0 + V * ic) * (pbw - pinf) * irho + R * dpbw * irc - 1.5 * V * V * (1.0 - V * ic * (1.0 / 3.0));
     double den = R * (1.0 - V * ic) + ph.mu4 * irc;
-    return num / den;
+    return num * frcp(den);
 }
 
 // Bubble-wall pressure p_bw = p_b - 4 mu Rdot/R - 2 sigma/R.
 __device__ inline double p_wall(const Phys &ph, double R, double V, double r0, double pg0)
 {
-    double iR = 1.0 / R;
+    double iR = frcp(R);
     double pb = pg0 * exp2(ph.kappa3 * log2(r0 * iR));
     return pb - ph.mu4 * V * iR - ph.sigma2 * iR;
 }

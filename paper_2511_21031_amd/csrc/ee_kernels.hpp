@@ -4,12 +4,15 @@
 //  k_prim     per cell: conserved -> primitive scratch P (rho, u, p_l, alpha,
 //             n, B, alpha source), bin moments, optional CFL wave-speed max,
 //             or the 8 diagnostic moments.  One thread per cell, coalesced
-//             structure-of-arrays loads; the bin loop is a uniform loop.
+//             structure-of-arrays loads, each bin read once.
 //  k_stage    the fused RK stage on a tile of cells: WENO5 + HLLC of the mixture
-//             (faces of every direction), then the bins streamed one at a time
-//             through LDS (upwind-side WENO5 of R and Rdot, passive HLLC flux,
-//             Keller--Miksis source, RK combine, store).
+//             on every face, then the bins streamed one at a time through LDS
+//             (upwind-side WENO5 of R and Rdot, passive HLLC flux,
+//             Keller--Miksis source, RK combine, store), with the next bin's
+//             global loads in flight while the current bin is reconstructed.
 #pragma once
+
+#include <type_traits>
 
 #include "device_common.hpp"
 
@@ -40,7 +43,7 @@ __global__ void __launch_bounds__(256) k_prim(const double *__restrict__ q, doub
         double rho = q[c];
         double u[3] = {0.0, 0.0, 0.0};
         double ke = 0.0;
-        double irho = 1.0 / rho;
+        double irho = frcp(rho);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             u[d] = q[(1 + d) * N + c] * irho;
@@ -59,33 +62,35 @@ __global__ void __launch_bounds__(256) k_prim(const double *__restrict__ q, doub
         bool negr = false;
         int badbin = -1;
         if (a > 0.0) {
-            double s = 0.0;
+            // One pass over the bins in the conserved variables x = nR, y = nRdot.  With
+            // R = x/n and Rdot = y/n every moment is a power of n times a sum that does
+            // not involve n, including the contents term:
+            //   R^3 p_b(R) = p_g0 R^3 (R0/R)^(3 kappa) = n^(3 kappa - 3) p_g0 x^3 (R0/x)^(3 kappa).
+            double s3 = 0.0, s2 = 0.0, s21 = 0.0, s32 = 0.0, sp = 0.0;
+#pragma unroll 4
             for (int i = 0; i < nb; ++i) {
                 double x = q[(iNR + i) * N + c];
-                s += bins.w[i] * (x * x * x);
+                double y = q[(iNV + i) * N + c];
                 if (!(x > 0.0) && !negr) {   // n > 0, so R_i has the sign of (nR)_i
                     negr = true;
                     badbin = i;
                 }
-            }
-            n = sqrt(FOUR_PI_3 * s / a);
-            double in = 1.0 / n;
-            for (int i = 0; i < nb; ++i) {
-                double R = q[(iNR + i) * N + c] * in;
-                double V = q[(iNV + i) * N + c] * in;
-                if (!(R > 0.0) && !negr) {
-                    negr = true;
-                    badbin = i;
-                }
-                double pbw = p_wall(ph, R, V, bins.r0[i], bins.pg0[i]);
                 double wi = bins.w[i];
-                double R2 = R * R, R3 = R2 * R;
-                M3 += wi * R3;
-                M2d += wi * R2 * V;
-                Mp += wi * R3 * pbw;
-                Mk += wi * R3 * V * V;
+                double x2 = x * x, x3 = x2 * x;
+                s3 += wi * x3;
+                s2 += wi * x2;
+                s21 += wi * x2 * y;
+                s32 += wi * x3 * y * y;
+                sp += wi * bins.pg0[i] * x3 * exp2(ph.kappa3 * log2(bins.r0[i] * frcp(x)));
             }
-            double iM3 = 1.0 / M3;
+            n = sqrt(FOUR_PI_3 * s3 / a);
+            double in = frcp(n);
+            double in2 = in * in, in3 = in2 * in;
+            M3 = s3 * in3;
+            M2d = s21 * in3;
+            Mk = s32 * in3 * in2;
+            Mp = exp2((ph.kappa3 - 3.0) * log2(n)) * sp - ph.mu4 * M2d - ph.sigma2 * s2 * in2;
+            double iM3 = frcp(M3);
             B = (Mp - rho * Mk) * iM3;
             Sa = 3.0 * a * M2d * iM3;
         } else {
@@ -173,8 +178,10 @@ __global__ void k_dt(Scalars *sc, double fixed_dt, double cfl, double *user_dt)
 // Fused RK stage
 // ---------------------------------------------------------------------------
 
-// Tile geometry.  Faces of direction d form the box (T + e_d); the "cross"
-// region holds the tile plus 3-cell halos along each active direction.
+// Tile geometry.  Faces of direction d form the box (T + e_d).  The "cross"
+// region holds the tile plus 3-cell halos along each active direction; bins
+// are staged into one "line" array per direction d, of extent T_d + 6 along d
+// and T_e across, so every face stencil is affine (constant stride).
 template <int D, int TX_, int TY_, int TZ_>
 struct Geo {
     static constexpr int TX = TX_, TY = (D > 1 ? TY_ : 1), TZ = (D > 2 ? TZ_ : 1);
@@ -188,37 +195,38 @@ struct Geo {
     static constexpr int C = T + 2 * (HX + HY + HZ);
     static constexpr int NC = D + 5;   // reconstructed core primitives
     static constexpr int NCF = D + 3;  // core fluxes: mass, momentum, energy, alpha
+    // line arrays
+    static constexpr int LX = (TX + 6) * TY * TZ;
+    static constexpr int LY = D > 1 ? TX * (TY + 6) * TZ : 0;
+    static constexpr int LZ = D > 2 ? TX * TY * (TZ + 6) : 0;
+    static constexpr int LOFF[3] = {0, LX, LX + LY};
+    static constexpr int L = LX + LY + LZ;
+    static constexpr int LSTRIDE[3] = {1, TX, TX * TY};
 
     template <int d>
     static constexpr int BX() { return TX + (d == 0); }
     template <int d>
     static constexpr int BY() { return TY + (d == 1); }
 
-    // cross-region index of local cell (i,j,k); only coordinate `d` may be outside the tile
+    // line-array index of local cell (i,j,k) in the array of direction d
+    // (coordinate d may lie in [-3, T_d + 3))
     template <int d>
-    __host__ __device__ static inline int cidx(int i, int j, int k)
+    __host__ __device__ static inline int lidx(int i, int j, int k)
     {
-        if (d == 0) {
-            if (i < 0) return T + (k * TY + j) * 3 + (i + 3);
-            if (i >= TX) return T + HX + (k * TY + j) * 3 + (i - TX);
-        } else if (d == 1) {
-            if (j < 0) return T + 2 * HX + (k * 3 + (j + 3)) * TX + i;
-            if (j >= TY) return T + 2 * HX + HY + (k * 3 + (j - TY)) * TX + i;
-        } else {
-            if (k < 0) return T + 2 * HX + 2 * HY + ((k + 3) * TY + j) * TX + i;
-            if (k >= TZ) return T + 2 * HX + 2 * HY + HZ + ((k - TZ) * TY + j) * TX + i;
-        }
-        return (k * TY + j) * TX + i;
+        if (d == 0) return LOFF[0] + (k * TY + j) * (TX + 6) + (i + 3);
+        if (d == 1) return LOFF[1] + (k * (TY + 6) + (j + 3)) * TX + i;
+        return LOFF[2] + ((k + 3) * TY + j) * TX + i;
     }
 
-    // local coordinates of cross-region index ci
-    __host__ __device__ static inline void cdecode(int ci, int &i, int &j, int &k)
+    // local coordinates of cross-region index ci; returns the halo direction
+    // (0,1,2) or -1 for a core cell
+    __host__ __device__ static inline int cdecode(int ci, int &i, int &j, int &k)
     {
         if (ci < T) {
             i = ci % TX;
             j = (ci / TX) % TY;
             k = ci / (TX * TY);
-            return;
+            return -1;
         }
         ci -= T;
         if (ci < 2 * HX) {
@@ -228,7 +236,7 @@ struct Geo {
             i = (ci % 3) + (hi ? TX : -3);
             j = r % TY;
             k = r / TY;
-            return;
+            return 0;
         }
         ci -= 2 * HX;
         if (ci < 2 * HY) {
@@ -238,7 +246,7 @@ struct Geo {
             int r = ci / TX;
             j = (r % 3) + (hi ? TY : -3);
             k = r / 3;
-            return;
+            return 1;
         }
         ci -= 2 * HY;
         int hi = ci >= HZ;
@@ -246,6 +254,7 @@ struct Geo {
         i = ci % TX;
         j = (ci / TX) % TY;
         k = (ci / (TX * TY)) + (hi ? TZ : -3);
+        return 2;
     }
 };
 
@@ -268,12 +277,11 @@ template <int D, int TX_, int TY_, int TZ_, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs A, Grid g, Phys ph, Bins bins)
 {
     using G = Geo<D, TX_, TY_, TZ_>;
-    constexpr int T = G::T, F = G::F, C = G::C, NC = G::NC, NCF = G::NCF;
-    constexpr int SCR = (NCF * F > 2 * C + 2 * F) ? NCF * F : 2 * C + 2 * F;
+    constexpr int T = G::T, F = G::F, C = G::C, NC = G::NC, NCF = G::NCF, L = G::L;
+    constexpr int CPT = (C + BLOCK - 1) / BLOCK;  // cross cells staged per thread
+    constexpr int SCR = (NCF * F > 2 * L + 2 * F) ? NCF * F : 2 * L + 2 * F;
     __shared__ double s_coef[F];
-    __shared__ double s_invn[C];
     __shared__ double s_scr[SCR];
-    __shared__ unsigned s_gidx[C];
     __shared__ unsigned char s_flag[F];
 
     // XCD-aware tile order: consecutive tiles land on the same XCD (blocks are dealt round-robin).
@@ -288,18 +296,32 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs A, Grid g, Phys ph, B
     const int nb = bins.nb;
     const int tid = threadIdx.x;
 
-    // ---- stage global indices and 1/n of the cross region ----
-    for (int ci = tid; ci < C; ci += BLOCK) {
-        int i, j, k;
-        G::cdecode(ci, i, j, k);
-        bool f = false;
-        int gx = map_coord(x0 + i, g.n[0], g.bc[0], f);
-        int gy = D > 1 ? map_coord(y0 + j, g.n[1], g.bc[1], f) : 0;
-        int gz = D > 2 ? map_coord(z0 + k, g.n[2], g.bc[2], f) : 0;
-        unsigned gi = (unsigned)gx + (unsigned)g.n[0] * ((unsigned)gy + (unsigned)g.n[1] * (unsigned)gz);
-        s_gidx[ci] = gi;
-        double n = A.P[PL<D>::N * N + gi];
-        s_invn[ci] = n > 0.0 ? 1.0 / n : 0.0;
+    // ---- per-thread staging plan: global index, 1/n and line-array slots of its cross cells ----
+    unsigned st_g[CPT];
+    double st_in[CPT];
+    int st_l[CPT][D];
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+        int ci = tid + r * BLOCK;
+        st_g[r] = 0;
+        st_in[r] = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) st_l[r][d] = -1;
+        if (ci < C) {
+            int i, j, k;
+            int h = G::cdecode(ci, i, j, k);
+            bool f = false;
+            int gx = map_coord(x0 + i, g.n[0], g.bc[0], f);
+            int gy = D > 1 ? map_coord(y0 + j, g.n[1], g.bc[1], f) : 0;
+            int gz = D > 2 ? map_coord(z0 + k, g.n[2], g.bc[2], f) : 0;
+            unsigned gi = (unsigned)gx + (unsigned)g.n[0] * ((unsigned)gy + (unsigned)g.n[1] * (unsigned)gz);
+            st_g[r] = gi;
+            double n = A.P[PL<D>::N * N + gi];
+            st_in[r] = n > 0.0 ? frcp(n) : 0.0;
+            if (h == 0 || h < 0) st_l[r][0] = G::template lidx<0>(i, j, k);
+            if (D > 1 && (h == 1 || h < 0)) st_l[r][D > 1 ? 1 : 0] = G::template lidx<(D > 1 ? 1 : 0)>(i, j, k);
+            if (D > 2 && (h == 2 || h < 0)) st_l[r][D > 2 ? 2 : 0] = G::template lidx<(D > 2 ? 2 : 0)>(i, j, k);
+        }
     }
 
     // ---- core faces: WENO5 of the mixture primitives, HLLC ----
@@ -403,6 +425,16 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs A, Grid g, Phys ph, B
     core_faces(std::integral_constant<int, 0>{});
     if (D > 1) core_faces(std::integral_constant<int, (D > 1 ? 1 : 0)>{});
     if (D > 2) core_faces(std::integral_constant<int, (D > 2 ? 2 : 0)>{});
+
+    // first bin's global loads go out while the core faces finish
+    const int iNR = D + 3, iNV = D + 3 + nb;
+    double pre_r[CPT], pre_v[CPT];
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+        bool ok = tid + r * BLOCK < C;
+        pre_r[r] = ok ? A.qk[(long long)iNR * N + st_g[r]] : 0.0;
+        pre_v[r] = ok ? A.qk[(long long)iNV * N + st_g[r]] : 0.0;
+    }
     __syncthreads();
 
     // ---- own cell: core divergence, sources, RK combine ----
@@ -421,24 +453,25 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs A, Grid g, Phys ph, B
         flo[2] = D > 2 ? G::OFF[2] + li + G::TX * (lj + G::TY * lk) : 0;
         fhi[2] = flo[2] + G::TX * G::TY;
     }
+    const int own_l = G::template lidx<0>(li, lj, lk);
     const double dt = A.rhs_mode ? 0.0 : *A.dtp;
-    double own_n = 0.0, own_pl = 0.0, own_rhol = 1.0, own_c = 1.0;
+    double own_n = 0.0, own_pl = 0.0, own_irhol = 1.0, own_ic = 1.0;
     if (active) {
-        double L[NCF];
+        double Lc[NCF];
 #pragma unroll
         for (int v = 0; v < NCF; ++v) {
             double acc = 0.0;
 #pragma unroll
             for (int d = 0; d < D; ++d) acc += (s_cf[v * F + flo[d]] - s_cf[v * F + fhi[d]]) * g.inv_dx[d];
-            L[v] = acc;
+            Lc[v] = acc;
         }
-        if (A.sources) L[D + 2] += A.P[PL<D>::SA * N + gc];
+        if (A.sources) Lc[D + 2] += A.P[PL<D>::SA * N + gc];
 #pragma unroll
         for (int v = 0; v < NCF; ++v) {
             long long o = (long long)v * N + gc;
-            if (A.rhs_mode) A.qo[o] = L[v];
+            if (A.rhs_mode) A.qo[o] = Lc[v];
             else {
-                double r = A.b * (A.qk[o] + dt * L[v]);
+                double r = A.b * (A.qk[o] + dt * Lc[v]);
                 if (A.a != 0.0) r += A.a * A.qn[o];
                 A.qo[o] = r;
             }
@@ -446,56 +479,79 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs A, Grid g, Phys ph, B
         own_n = A.P[PL<D>::N * N + gc];
         own_pl = A.P[PL<D>::PLQ * N + gc];
         double a = A.P[PL<D>::A * N + gc];
-        own_rhol = A.P[PL<D>::RHO * N + gc] / (1.0 - a);
-        own_c = sqrt(ph.gamma * (own_pl + ph.pi_inf) / own_rhol);
+        double rhol = A.P[PL<D>::RHO * N + gc] / (1.0 - a);
+        own_irhol = frcp(rhol);
+        own_ic = frcp(sqrt(ph.gamma * (own_pl + ph.pi_inf) * own_irhol));
     }
     __syncthreads();  // s_cf is reused below
 
-    // ---- bins, one at a time ----
-    double *s_R = s_scr, *s_V = s_scr + C, *s_fR = s_scr + 2 * C, *s_fV = s_scr + 2 * C + F;
-    const int iNR = D + 3, iNV = D + 3 + nb;
+    // ---- bins, one at a time: stage -> faces -> cells; next bin's loads overlap the faces ----
+    double *s_R = s_scr, *s_V = s_scr + L, *s_fR = s_scr + 2 * L, *s_fV = s_scr + 2 * L + F;
     for (int ib = 0; ib < nb; ++ib) {
         const double r0 = bins.r0[ib];
-        for (int ci = tid; ci < C; ci += BLOCK) {
-            unsigned gi = s_gidx[ci];
-            double in = s_invn[ci];
-            double nR = A.qk[(long long)(iNR + ib) * N + gi];
-            double nV = A.qk[(long long)(iNV + ib) * N + gi];
-            s_R[ci] = in > 0.0 ? nR * in : r0;
-            s_V[ci] = in > 0.0 ? nV * in : 0.0;
+#pragma unroll
+        for (int r = 0; r < CPT; ++r) {
+            if (tid + r * BLOCK < C) {
+                double in = st_in[r];
+                double Rv = in > 0.0 ? pre_r[r] * in : r0;
+                double Vv = in > 0.0 ? pre_v[r] * in : 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    int l = st_l[r][d];
+                    if (l >= 0) {
+                        s_R[l] = Rv;
+                        s_V[l] = Vv;
+                    }
+                }
+            }
         }
         __syncthreads();
+        double own_R = s_R[own_l], own_V = s_V[own_l];
+        if (ib + 1 < nb) {
+#pragma unroll
+            for (int r = 0; r < CPT; ++r) {
+                bool ok = tid + r * BLOCK < C;
+                pre_r[r] = ok ? A.qk[(long long)(iNR + ib + 1) * N + st_g[r]] : 0.0;
+                pre_v[r] = ok ? A.qk[(long long)(iNV + ib + 1) * N + st_g[r]] : 0.0;
+            }
+        }
         auto bin_faces = [&](auto dtag) {
             constexpr int d = decltype(dtag)::value;
             constexpr int BX = G::template BX<d>(), BY = G::template BY<d>();
             constexpr int FD = (d == 0) ? G::FX : (d == 1 ? G::FY : G::FZ);
+            constexpr int S = G::LSTRIDE[d];
             for (int t = tid; t < FD; t += BLOCK) {
-                int lc[3] = {t % BX, (t / BX) % BY, t / (BX * BY)};
+                int fi = t % BX, fj = (t / BX) % BY, fk = t / (BX * BY);
                 const int slot = G::OFF[d] + t;
                 unsigned fl = s_flag[slot];
-                int side = fl & 1;
-                // upwind-side stencil: L uses f-3..f+1, R uses f+2..f-2 (mirrored)
-                int base = side ? lc[d] + 2 : lc[d] - 3;
-                int step = side ? -1 : 1;
-                double r[5], v[5];
+                bool right = fl & 1;
+                // cells f-3 .. f+2 along d start at the face's own coordinates in the line array
+                int p[3] = {fi, fj, fk};
+                p[d] -= 3;
+                const int base = G::template lidx<d>(p[0], p[1], p[2]);
+                double r6[6], v6[6];
+#pragma unroll
+                for (int o = 0; o < 6; ++o) {
+                    r6[o] = s_R[base + o * S];
+                    v6[o] = s_V[base + o * S];
+                }
+                // upwind side: L uses cells f-3..f+1, R the mirrored f+2..f-2
+                double rr[5], vv[5];
 #pragma unroll
                 for (int o = 0; o < 5; ++o) {
-                    int p[3] = {lc[0], lc[1], lc[2]};
-                    p[d] = base + o * step;
-                    int ci = G::template cidx<d>(p[0], p[1], p[2]);
-                    r[o] = s_R[ci];
-                    v[o] = s_V[ci];
+                    rr[o] = right ? r6[5 - o] : r6[o];
+                    vv[o] = right ? v6[5 - o] : v6[o];
                 }
                 double RK, VK;
                 if (fl & 2) {
-                    RK = r[2];
-                    VK = v[2];
+                    RK = rr[2];
+                    VK = vv[2];
                 } else {
-                    RK = weno5(r[0], r[1], r[2], r[3], r[4]);
-                    VK = weno5(v[0], v[1], v[2], v[3], v[4]);
+                    RK = weno5(rr[0], rr[1], rr[2], rr[3], rr[4]);
+                    VK = weno5(vv[0], vv[1], vv[2], vv[3], vv[4]);
                     if (!(RK > 0.0)) {
-                        RK = r[2];
-                        VK = v[2];
+                        RK = rr[2];
+                        VK = vv[2];
                     }
                 }
                 double cf = s_coef[slot];
@@ -515,9 +571,8 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs A, Grid g, Phys ph, B
                 LV += (s_fV[flo[d]] - s_fV[fhi[d]]) * g.inv_dx[d];
             }
             if (A.sources && own_n > 0.0) {
-                double R = s_R[tid], V = s_V[tid];
-                LR += own_n * V;
-                LV += own_n * km_rddot(ph, R, V, r0, bins.pg0[ib], own_pl, own_rhol, own_c);
+                LR += own_n * own_V;
+                LV += own_n * km_rddot(ph, own_R, own_V, r0, bins.pg0[ib], own_pl, own_irhol, own_ic);
             }
             long long oR = (long long)(iNR + ib) * N + gc, oV = (long long)(iNV + ib) * N + gc;
             if (A.rhs_mode) {
@@ -534,7 +589,8 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs A, Grid g, Phys ph, B
                 A.qo[oV] = xv;
             }
         }
-        __syncthreads();
+        // the next bin's staging writes s_R/s_V only after every thread passed the barrier above,
+        // and s_fR/s_fV are rewritten only after the next staging barrier.
     }
 }
 

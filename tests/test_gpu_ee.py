@@ -216,3 +216,20 @@ def test_error_word_nonfinite_and_negative_radius(torch, bub, orc):
     ctx.moments(q)
     code, cell, b = ctx.last_error()
     assert code == -5 and cell == 40 and b == 1
+
+
+@pytest.mark.parametrize("kind", ["c1", "2d_ragged_periodic", "3d_ragged_reflective"])
+def test_tile_shapes_give_identical_results(torch, bub, orc, kind):
+    """Every compiled tile shape computes each face flux with the same arithmetic: bitwise equal RHS."""
+    case = _case_grid(kind)
+    pb = orc.problem_from_case(case)
+    q = _gpu(torch, perturb_bins(orc.init_state(pb, case.prim), case.ndim, case.nb, seed=4))
+    ctx = bub.context_from_case(case)
+    outs = []
+    for v in range(len(ctx.tiles())):
+        ctx.tile = v
+        outs.append(ctx.rhs_stage(q).cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    best, ms = ctx.autotune(q, reps=2)
+    assert ctx.tile == best and 0 <= best < len(ms) and all(m > 0 for m in ms)

@@ -2,13 +2,15 @@
 //
 // For every tile shape the kernels are instantiated with, and a set of grid
 // sizes and boundary kinds, enumerate exactly the indices k_stage computes:
-// the cross-region (LDS) round trip, the 5-point upwind stencils of every face
-// on both sides, the face slots of every owned cell, and the ghost-cell map of
-// every global load.  Exit status 0 only if every index is in bounds and
-// points at the intended cell.
+// the staging plan (cross region -> per-direction line arrays in LDS), the
+// 6-cell stencils of every face, the face slots of every owned cell, and the
+// ghost-cell map of every global load.  Exit status 0 only if every index is
+// in bounds and points at the intended cell.
 #include <cstdio>
 #include <cstdlib>
+#include <map>
 #include <set>
+#include <tuple>
 
 #include "ee_kernels.hpp"
 
@@ -27,50 +29,59 @@ template <int D, int TX, int TY, int TZ>
 void check_tile()
 {
     using G = Geo<D, TX, TY, TZ>;
-    // 1) cross-region round trip, unique and in range
-    std::set<int> seen;
+    // 1) staging plan: slot -> cell; every slot in range and written once
+    std::map<int, std::tuple<int, int, int>> slot_cell;
     for (int ci = 0; ci < G::C; ++ci) {
         int i, j, k;
-        G::cdecode(ci, i, j, k);
+        int h = G::cdecode(ci, i, j, k);
         int out = (i < 0 || i >= G::TX) + (j < 0 || j >= G::TY) + (k < 0 || k >= G::TZ);
-        CHECK(out <= 1, "D%d ci %d decodes to two halos\n", D, ci);
-        int back;
-        if (i < 0 || i >= G::TX) back = G::template cidx<0>(i, j, k);
-        else if (j < 0 || j >= G::TY) back = G::template cidx<1>(i, j, k);
-        else back = G::template cidx<2>(i, j, k);
-        CHECK(back == ci, "D%d round trip %d -> (%d,%d,%d) -> %d\n", D, ci, i, j, k, back);
+        CHECK(out == (h >= 0 ? 1 : 0), "D%d ci %d halo kind\n", D, ci);
         CHECK(i >= -3 && i < G::TX + 3 && j >= -3 && j < G::TY + 3 && k >= -3 && k < G::TZ + 3, "range\n");
-        seen.insert(ci);
+        int slots[3] = {-1, -1, -1};
+        if (h == 0 || h < 0) slots[0] = G::template lidx<0>(i, j, k);
+        if (D > 1 && (h == 1 || h < 0)) slots[1] = G::template lidx<(D > 1 ? 1 : 0)>(i, j, k);
+        if (D > 2 && (h == 2 || h < 0)) slots[2] = G::template lidx<(D > 2 ? 2 : 0)>(i, j, k);
+        for (int d = 0; d < D; ++d) {
+            int l = slots[d];
+            if (l < 0) continue;
+            CHECK(l >= G::LOFF[d] && l < G::LOFF[d] + (d == 0 ? G::LX : d == 1 ? G::LY : G::LZ),
+                  "D%d slot %d outside array %d\n", D, l, d);
+            CHECK(slot_cell.count(l) == 0, "D%d slot %d written twice\n", D, l);
+            slot_cell[l] = std::make_tuple(i, j, k);
+        }
+        CHECK(h >= 0 || slots[0] >= 0, "core cell without x slot\n");
     }
-    CHECK((int)seen.size() == G::C, "cross size\n");
-    // 2) face tasks: slots and both upwind stencils
+    // 2) face tasks: slots and the 6-cell stencil along d
     auto faces = [&](auto dtag) {
         constexpr int d = decltype(dtag)::value;
         constexpr int BX = G::template BX<d>(), BY = G::template BY<d>();
         constexpr int FD = d == 0 ? G::FX : (d == 1 ? G::FY : G::FZ);
+        constexpr int S = G::LSTRIDE[d];
         for (int t = 0; t < FD; ++t) {
-            int lc[3] = {t % BX, (t / BX) % BY, t / (BX * BY)};
+            int fi = t % BX, fj = (t / BX) % BY, fk = t / (BX * BY);
             int slot = G::OFF[d] + t;
             CHECK(slot >= 0 && slot < G::F, "slot\n");
-            for (int side = 0; side < 2; ++side) {
-                int base = side ? lc[d] + 2 : lc[d] - 3;
-                int step = side ? -1 : 1;
-                for (int o = 0; o < 5; ++o) {
-                    int p[3] = {lc[0], lc[1], lc[2]};
-                    p[d] = base + o * step;
-                    int ci = G::template cidx<d>(p[0], p[1], p[2]);
-                    CHECK(ci >= 0 && ci < G::C, "D%d dir %d face %d stencil ci %d\n", D, d, t, ci);
-                    int a, b, c;
-                    G::cdecode(ci, a, b, c);
-                    CHECK(a == p[0] && b == p[1] && c == p[2], "D%d dir %d stencil cell mismatch\n", D, d);
-                }
+            int p[3] = {fi, fj, fk};
+            p[d] -= 3;
+            int base = G::template lidx<d>(p[0], p[1], p[2]);
+            for (int o = 0; o < 6; ++o) {
+                int l = base + o * S;
+                CHECK(l >= 0 && l < G::L, "D%d dir %d face %d stencil slot %d\n", D, d, t, l);
+                auto it = slot_cell.find(l);
+                CHECK(it != slot_cell.end(), "D%d dir %d face %d reads unstaged slot %d\n", D, d, t, l);
+                if (it == slot_cell.end()) continue;
+                int want[3] = {fi, fj, fk};
+                want[d] += o - 3;
+                CHECK(std::get<0>(it->second) == want[0] && std::get<1>(it->second) == want[1] &&
+                          std::get<2>(it->second) == want[2],
+                      "D%d dir %d face %d stencil %d reads the wrong cell\n", D, d, t, o);
             }
         }
     };
     faces(std::integral_constant<int, 0>{});
     if (D > 1) faces(std::integral_constant<int, (D > 1 ? 1 : 0)>{});
     if (D > 2) faces(std::integral_constant<int, (D > 2 ? 2 : 0)>{});
-    // 3) owned cells: lo/hi face slots decode to the cell's faces
+    // 3) owned cells: lo/hi face slots decode to the cell's faces; own slot holds the cell
     for (int tid = 0; tid < G::T; ++tid) {
         int li = tid % G::TX, lj = (tid / G::TX) % G::TY, lk = tid / (G::TX * G::TY);
         int flo[3], fhi[3];
@@ -92,7 +103,9 @@ void check_tile()
                 CHECK(ch[e] == me[e] + (e == d), "hi face coord\n");
             }
         }
-        CHECK(G::template cidx<0>(li, lj, lk) == tid, "own cell is core index tid\n");
+        int ol = G::template lidx<0>(li, lj, lk);
+        auto it = slot_cell.find(ol);
+        CHECK(it != slot_cell.end() && it->second == std::make_tuple(li, lj, lk), "own slot\n");
     }
 }
 
@@ -140,17 +153,50 @@ void check_grid(int nx, int ny, int nz, int bc)
     CHECK((int)tiles.size() == ntiles, "tile cover %zu of %d\n", tiles.size(), ntiles);
 }
 
-int main()
+template <int TX>
+void check_1d()
 {
-    check_tile<1, 255, 1, 1>();
-    check_tile<2, 32, 8, 1>();
-    check_tile<3, 8, 8, 4>();
+    check_tile<1, TX, 1, 1>();
+    for (int bc = 0; bc < 2; ++bc)
+        for (int nx : {bc ? 3 : 1, 5, TX, TX + 1, 400, 1000}) check_grid<1, TX, 1, 1>(nx, 1, 1, bc);
+}
+
+template <int TX, int TY>
+void check_2d()
+{
+    check_tile<2, TX, TY, 1>();
     for (int bc = 0; bc < 2; ++bc) {
         int lo = bc ? 3 : 1;
-        for (int nx : {lo, 5, 255, 256, 400, 1000}) check_grid<1, 255, 1, 1>(nx, 1, 1, bc);
-        for (int nx : {lo, 7, 32, 33, 70}) for (int ny : {lo + 1, 8, 9, 37}) check_grid<2, 32, 8, 1>(nx, ny, 1, bc);
-        for (int nx : {lo, 8, 20}) for (int ny : {lo, 9}) for (int nz : {lo + 1, 4, 11}) check_grid<3, 8, 8, 4>(nx, ny, nz, bc);
+        for (int nx : {lo, 7, TX, TX + 1, 70})
+            for (int ny : {lo + 1, TY, TY + 1, 37}) check_grid<2, TX, TY, 1>(nx, ny, 1, bc);
     }
+}
+
+template <int TX, int TY, int TZ>
+void check_3d()
+{
+    check_tile<3, TX, TY, TZ>();
+    for (int bc = 0; bc < 2; ++bc) {
+        int lo = bc ? 3 : 1;
+        for (int nx : {lo, TX, 20})
+            for (int ny : {lo, TY + 1})
+                for (int nz : {lo + 1, TZ, 11}) check_grid<3, TX, TY, TZ>(nx, ny, nz, bc);
+    }
+}
+
+int main()
+{
+    // every tile shape the library instantiates
+    check_1d<255>();
+    check_1d<127>();
+    check_1d<511>();
+    check_2d<32, 8>();
+    check_2d<31, 8>();
+    check_2d<64, 4>();
+    check_2d<32, 16>();
+    check_3d<8, 8, 4>();
+    check_3d<16, 4, 4>();
+    check_3d<8, 4, 4>();
     std::printf("%s (%d failures)\n", failures ? "FAIL" : "OK", failures);
     return failures ? 1 : 0;
 }
