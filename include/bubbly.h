@@ -136,6 +136,18 @@ int bub_rk3_step(bub_ctx *ctx, double *q, double *work, double dt, double *dt_de
  * quadrature sum_i w_i (.)_i. */
 int bub_moments(bub_ctx *ctx, const double *q, double *out, void *stream);
 
+/* Bubble half of the Strang splitting (Sec. 3), in place on q: every (cell, bin)
+ * advances (R, Rdot) over `tau` by the Keller--Miksis equation with the cell's
+ * p_l, rho_l and c frozen at entry, using adaptive embedded SSP-RK3 / Heun-RK2
+ * sub-steps (relative error of R and Rdot below opts.sub_rtol, Rdot floored at
+ * 1e-3 sqrt(p0/rho0); step factor 0.9 (rtol/err)^(1/3) clamped to [1/4, 4],
+ * first sub-step = tau; at most opts.max_substeps attempts, else BUB_ESUBSTEP on
+ * the error word).  n is held fixed: (nR)_i = n R_i, (nRdot)_i = n Rdot_i, and
+ * alpha is rescaled by mean(R^3)_new / mean(R^3)_old.  tau > 0 (seconds).
+ * nsub (device int32 [nb][N], may be NULL) receives the accepted sub-step count
+ * of every (cell, bin).  Valid in either bubble mode. */
+int bub_bubble_advance(bub_ctx *ctx, double *q, double tau, int32_t *nsub, void *stream);
+
 /* Synchronises `stream`, then reports and clears the sticky device error word:
  * *code (BUB_OK or a device BUB_E* code), *cell (first failing cell or -1),
  * *bin (failing bin or -1).  Any output pointer may be NULL. */

@@ -64,6 +64,7 @@ _SIGS = {
     "bub_moments": [_vp, _vp, _vp, _vp],
     "bub_last_error": [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_int),
                        _vp],
+    "bub_bubble_advance": [_vp, _vp, ctypes.c_double, _vp, _vp],
     "bub_tile_count": [_vp, ctypes.POINTER(ctypes.c_int)],
     "bub_tile_info": [_vp, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4,
     "bub_tile_set": [_vp, ctypes.c_int],
@@ -206,6 +207,14 @@ class Context:
         out = torch.empty((8, self.ncells), dtype=torch.float64, device=q.device) if out is None else out
         _check(lib().bub_moments(self._h, _ptr(q), _ptr(out), _stream(stream)), "bub_moments")
         return out
+
+    def bubble_advance(self, q: torch.Tensor, tau: float, nsub: torch.Tensor | None = None, stream=None):
+        """Bubble half of the Strang splitting over tau, in place; nsub (int32 [nb][N]) gets sub-step counts."""
+        if nsub is not None and (nsub.dtype != torch.int32 or not nsub.is_cuda or nsub.numel() != self.nb * self.ncells):
+            raise ValueError("nsub must be an int32 GPU tensor of nb*N entries")
+        _check(lib().bub_bubble_advance(self._h, _ptr(q), float(tau),
+                                        None if nsub is None else _vp(nsub.data_ptr()), _stream(stream)),
+               "bub_bubble_advance")
 
     def tiles(self):
         """List of (tx, ty, tz, block) stage-kernel tile shapes for this dimensionality."""

@@ -11,6 +11,7 @@
 
 #include "bubbly.h"
 #include "ee_kernels.hpp"
+#include "split_kernels.hpp"
 #include "ctx.hpp"
 
 using namespace bub;
@@ -129,6 +130,28 @@ int launch_stage_v(bub_ctx *c, StageArgs A, hipStream_t s)
     long pr = prof_begin(c, BUB_K_STAGE, s);
     hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK>), dim3(8 * A.nblk_per_xcd),
                        dim3(TC::BLOCK), 0, s, A, c->g, c->ph, c->bt);
+    prof_end(c, pr, s);
+    return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
+}
+
+int bubble(bub_ctx *c, double *q, const double *taup, double tau_scale, double tau_fixed, int *nsub,
+           hipStream_t s)
+{
+    BubbleArgs B{};
+    B.q = q;
+    B.taup = taup;
+    B.tau_scale = tau_scale;
+    B.tau_fixed = tau_fixed;
+    B.rtol = c->opts.sub_rtol > 0.0 ? c->opts.sub_rtol : 1e-4;
+    B.max_substeps = c->opts.max_substeps > 0 ? c->opts.max_substeps : 10000;
+    B.nsub = nsub;
+    int nbk = blocks_for(c->g.N);
+    long pr = prof_begin(c, BUB_K_OTHER, s);
+    switch (c->ndim) {
+    case 1: hipLaunchKernelGGL((k_bubble<1>), dim3(nbk), dim3(256), 0, s, B, c->g, c->ph, c->bt, c->d_sc); break;
+    case 2: hipLaunchKernelGGL((k_bubble<2>), dim3(nbk), dim3(256), 0, s, B, c->g, c->ph, c->bt, c->d_sc); break;
+    default: hipLaunchKernelGGL((k_bubble<3>), dim3(nbk), dim3(256), 0, s, B, c->g, c->ph, c->bt, c->d_sc); break;
+    }
     prof_end(c, pr, s);
     return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
 }
@@ -354,7 +377,7 @@ int bub_rk3_step(bub_ctx *c, double *q, double *work, double dt, double *dt_dev,
     if (!c || !q || !work) return BUB_EINVAL;
     if (!(dt == dt) || dt == INFINITY) return BUB_EINVAL;
     if (c->opts.precision != BUB_PREC_FP64) return BUB_EUNSUPPORTED;
-    if (c->opts.bubble_mode != BUB_BUBBLES_UNSPLIT) return BUB_EUNSUPPORTED;
+    const bool split = c->opts.bubble_mode == BUB_BUBBLES_SPLIT;
     const size_t M = (size_t)c->nvar * (size_t)c->N;
     double *w1 = work, *w2 = work + M;
     if ((q >= work && q < work + 2 * M) || (work >= q && work < q + M)) return BUB_EINVAL;
@@ -366,11 +389,16 @@ int bub_rk3_step(bub_ctx *c, double *q, double *work, double dt, double *dt_dev,
     hipLaunchKernelGGL(k_dt, dim3(1), dim3(1), 0, s, c->d_sc, cfl ? 0.0 : dt, c->opts.cfl, dt_dev);
     prof_end(c, pr, s);
     HIP_OK(hipGetLastError());
+    if (split) {
+        // S_b(dt/2) first; the flux part then starts from the primitives of the advanced state
+        if ((rc = bubble(c, q, &c->d_sc->dt, 0.5, 0.0, nullptr, s))) return rc;
+        if ((rc = prim(c, q, c->d_P, PRIM_ONLY, s))) return rc;
+    }
     StageArgs A{};
     A.P = c->d_P;
     A.dtp = &c->d_sc->dt;
     A.rhs_mode = 0;
-    A.sources = 1;
+    A.sources = split ? 0 : 1;
     // stage 1: u1 = u^n + dt L(u^n)
     A.qk = q; A.qn = nullptr; A.qo = w1; A.a = 0.0; A.b = 1.0;
     if ((rc = stage(c, A, s))) return rc;
@@ -381,7 +409,15 @@ int bub_rk3_step(bub_ctx *c, double *q, double *work, double dt, double *dt_dev,
     // stage 3: u^{n+1} = 1/3 u^n + 2/3 (u2 + dt L(u2)), written over u^n (own-cell reads only)
     if ((rc = prim(c, w2, c->d_P, PRIM_ONLY, s))) return rc;
     A.qk = w2; A.qn = q; A.qo = q; A.a = 1.0 / 3.0; A.b = 2.0 / 3.0;
-    return stage(c, A, s);
+    if ((rc = stage(c, A, s))) return rc;
+    if (split) rc = bubble(c, q, &c->d_sc->dt, 0.5, 0.0, nullptr, s);   // S_b(dt/2)
+    return rc;
+}
+
+int bub_bubble_advance(bub_ctx *c, double *q, double tau, int32_t *nsub, void *stream)
+{
+    if (!c || !q || !(tau > 0.0) || tau == INFINITY) return BUB_EINVAL;
+    return bubble(c, q, nullptr, 0.0, tau, nsub, (hipStream_t)stream);
 }
 
 int bub_last_error(bub_ctx *c, int *code, int64_t *cell, int *bin, void *stream)
