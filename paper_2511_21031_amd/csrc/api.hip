@@ -12,6 +12,7 @@
 #include "bubbly.h"
 #include "ee_kernels.hpp"
 #include "split_kernels.hpp"
+#include "stage_kernel.hpp"
 #include "ctx.hpp"
 
 using namespace bub;
@@ -117,8 +118,8 @@ int launch_prim(bub_ctx *c, const double *q, double *out, int mode, hipStream_t 
     return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
 }
 
-template <int D, int V>
-int launch_stage_v(bub_ctx *c, StageArgs A, hipStream_t s)
+template <int D, int V, typename TF>
+int launch_stage_t(bub_ctx *c, StageArgs A, hipStream_t s)
 {
     using TC = Tile<D, V>;
     using G = Geo<D, TC::TX, TC::TY, TC::TZ>;
@@ -128,10 +129,17 @@ int launch_stage_v(bub_ctx *c, StageArgs A, hipStream_t s)
     A.ntiles = A.ntile[0] * A.ntile[1] * A.ntile[2];
     A.nblk_per_xcd = (A.ntiles + 7) / 8;
     long pr = prof_begin(c, BUB_K_STAGE, s);
-    hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK>), dim3(8 * A.nblk_per_xcd),
+    hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF>), dim3(8 * A.nblk_per_xcd),
                        dim3(TC::BLOCK), 0, s, A, c->g, c->ph, c->bt);
     prof_end(c, pr, s);
     return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
+}
+
+template <int D, int V>
+int launch_stage_v(bub_ctx *c, StageArgs A, hipStream_t s)
+{
+    if (c->opts.precision == BUB_PREC_MIXED) return launch_stage_t<D, V, float>(c, A, s);
+    return launch_stage_t<D, V, double>(c, A, s);
 }
 
 int bubble(bub_ctx *c, double *q, const double *taup, double tau_scale, double tau_fixed, int *nsub,
@@ -355,7 +363,6 @@ int bub_moments(bub_ctx *c, const double *q, double *out, void *stream)
 int bub_rhs_stage(bub_ctx *c, const double *q, double *rhs, void *stream)
 {
     if (!c || !q || !rhs || q == rhs) return BUB_EINVAL;
-    if (c->opts.precision != BUB_PREC_FP64) return BUB_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     int rc = prim(c, q, c->d_P, PRIM_ONLY, s);
     if (rc) return rc;
@@ -376,7 +383,6 @@ int bub_rk3_step(bub_ctx *c, double *q, double *work, double dt, double *dt_dev,
 {
     if (!c || !q || !work) return BUB_EINVAL;
     if (!(dt == dt) || dt == INFINITY) return BUB_EINVAL;
-    if (c->opts.precision != BUB_PREC_FP64) return BUB_EUNSUPPORTED;
     const bool split = c->opts.bubble_mode == BUB_BUBBLES_SPLIT;
     const size_t M = (size_t)c->nvar * (size_t)c->N;
     double *w1 = work, *w2 = work + M;

@@ -115,30 +115,37 @@ __device__ inline double weno5(double v0, double v1, double v2, double v3, doubl
     return (a0 * q0 + a1 * q1 + a2 * q2) * frcp(a0 + a1 + a2);
 }
 
-// Generic-precision variant (used by the mixed form).
-template <typename T>
-__device__ inline T weno5_t(T v0, T v1, T v2, T v3, T v4)
+// FP32 WENO5-JS for the mixed form.  The weights are taken in ratio form,
+// a_k = d_k ((eps + beta_min) / (eps + beta_k))^2, which equals the JS weights
+// after normalisation and stays inside the FP32 range (the product form of the
+// FP64 version would overflow or underflow).
+__device__ inline float weno5(float v0, float v1, float v2, float v3, float v4)
 {
-    const T eps = T(1e-16);
-    const T c16 = T(1.0 / 6.0);
-    const T c1312 = T(13.0 / 12.0);
-    T q0 = (T(2) * v0 - T(7) * v1 + T(11) * v2) * c16;
-    T q1 = (-v1 + T(5) * v2 + T(2) * v3) * c16;
-    T q2 = (T(2) * v2 + T(5) * v3 - v4) * c16;
-    T d0 = v0 - T(2) * v1 + v2, e0 = v0 - T(4) * v1 + T(3) * v2;
-    T d1 = v1 - T(2) * v2 + v3, e1 = v1 - v3;
-    T d2 = v2 - T(2) * v3 + v4, e2 = T(3) * v2 - T(4) * v3 + v4;
-    T b0 = c1312 * d0 * d0 + T(0.25) * e0 * e0;
-    T b1 = c1312 * d1 * d1 + T(0.25) * e1 * e1;
-    T b2 = c1312 * d2 * d2 + T(0.25) * e2 * e2;
-    T s0 = (eps + b0) * (eps + b0);
-    T s1 = (eps + b1) * (eps + b1);
-    T s2 = (eps + b2) * (eps + b2);
-    T a0 = T(0.1) * (s1 * s2);
-    T a1 = T(0.6) * (s0 * s2);
-    T a2 = T(0.3) * (s0 * s1);
-    return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+    const float eps = 1e-16f;
+    const float c16 = 1.0f / 6.0f;
+    const float c1312 = 13.0f / 12.0f;
+    float q0 = (2.0f * v0 - 7.0f * v1 + 11.0f * v2) * c16;
+    float q1 = (-v1 + 5.0f * v2 + 2.0f * v3) * c16;
+    float q2 = (2.0f * v2 + 5.0f * v3 - v4) * c16;
+    float d0 = v0 - 2.0f * v1 + v2, e0 = v0 - 4.0f * v1 + 3.0f * v2;
+    float d1 = v1 - 2.0f * v2 + v3, e1 = v1 - v3;
+    float d2 = v2 - 2.0f * v3 + v4, e2 = 3.0f * v2 - 4.0f * v3 + v4;
+    float s0 = eps + (c1312 * d0 * d0 + 0.25f * e0 * e0);
+    float s1 = eps + (c1312 * d1 * d1 + 0.25f * e1 * e1);
+    float s2 = eps + (c1312 * d2 * d2 + 0.25f * e2 * e2);
+    float sm = fminf(s0, fminf(s1, s2));
+    float r0 = sm * __builtin_amdgcn_rcpf(s0), r1 = sm * __builtin_amdgcn_rcpf(s1), r2 = sm * __builtin_amdgcn_rcpf(s2);
+    float a0 = 0.1f * r0 * r0, a1 = 0.6f * r1 * r1, a2 = 0.3f * r2 * r2;
+    return (a0 * q0 + a1 * q1 + a2 * q2) * __builtin_amdgcn_rcpf(a0 + a1 + a2);
 }
+
+// Reciprocal, square root and division in the reconstruction precision.
+__device__ inline double trcp(double x) { return frcp(x); }
+__device__ inline float trcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double tsqrt(double x) { return sqrt(x); }
+__device__ inline float tsqrt(float x) { return __builtin_sqrtf(x); }
+__device__ inline double tdiv(double a, double b) { return a / b; }
+__device__ inline float tdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
 // Keller--Miksis wall acceleration (eq. keller_miksis) with polytropic
 // contents; the R-ddot part of d(p_bw)/dt that comes from the viscous term is

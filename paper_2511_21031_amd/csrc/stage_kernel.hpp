@@ -1,0 +1,445 @@
+// The fused RK-stage kernel of the ensemble-averaged model (gfx950).
+//
+// One workgroup owns a tile of cells.  It computes the WENO5 + HLLC flux of the
+// mixture on every face of the tile (all directions), then streams the bins
+// one at a time through LDS: stage R = nR/n and Rdot = nRdot/n of the tile and
+// its 3-cell halos, reconstruct the upwind side of every face (the passive
+// HLLC flux of a bin variable needs only that side), difference the fluxes,
+// add the Keller--Miksis source of the owned cell and write the RK combine.
+// The next bin's global loads are in flight while the current bin is
+// reconstructed.
+//
+// TF is the reconstruction precision: double (plain FP64) or float (the mixed
+// form: reconstruction, Riemann solver and flux differences in FP32; the
+// primitive pass, moments, Keller--Miksis and the RK combine stay FP64).
+#pragma once
+
+#include <type_traits>
+
+#include "device_common.hpp"
+#include "ee_kernels.hpp"
+
+namespace bub {
+
+// Tile geometry.  Faces of direction d form the box (T + e_d).  The "cross"
+// region holds the tile plus 3-cell halos along each active direction; bins
+// are staged into one "line" array per direction d, of extent T_d + 6 along d
+// and T_e across, so every face stencil is affine (constant stride).
+template <int D, int TX_, int TY_, int TZ_>
+struct Geo {
+    static constexpr int TX = TX_, TY = (D > 1 ? TY_ : 1), TZ = (D > 2 ? TZ_ : 1);
+    static constexpr int T = TX * TY * TZ;
+    static constexpr int FX = (TX + 1) * TY * TZ;
+    static constexpr int FY = D > 1 ? TX * (TY + 1) * TZ : 0;
+    static constexpr int FZ = D > 2 ? TX * TY * (TZ + 1) : 0;
+    static constexpr int F = FX + FY + FZ;
+    static constexpr int OFF[3] = {0, FX, FX + FY};
+    static constexpr int HX = 3 * TY * TZ, HY = D > 1 ? 3 * TX * TZ : 0, HZ = D > 2 ? 3 * TX * TY : 0;
+    static constexpr int C = T + 2 * (HX + HY + HZ);
+    static constexpr int NC = D + 5;   // reconstructed core primitives
+    static constexpr int NCF = D + 3;  // core fluxes: mass, momentum, energy, alpha
+    // line arrays
+    static constexpr int LX = (TX + 6) * TY * TZ;
+    static constexpr int LY = D > 1 ? TX * (TY + 6) * TZ : 0;
+    static constexpr int LZ = D > 2 ? TX * TY * (TZ + 6) : 0;
+    static constexpr int LOFF[3] = {0, LX, LX + LY};
+    static constexpr int L = LX + LY + LZ;
+    static constexpr int LSTRIDE[3] = {1, TX, TX * TY};
+
+    template <int d>
+    static constexpr int BX() { return TX + (d == 0); }
+    template <int d>
+    static constexpr int BY() { return TY + (d == 1); }
+
+    // line-array index of local cell (i,j,k) in the array of direction d
+    // (coordinate d may lie in [-3, T_d + 3))
+    template <int d>
+    __host__ __device__ static inline int lidx(int i, int j, int k)
+    {
+        if (d == 0) return LOFF[0] + (k * TY + j) * (TX + 6) + (i + 3);
+        if (d == 1) return LOFF[1] + (k * (TY + 6) + (j + 3)) * TX + i;
+        return LOFF[2] + ((k + 3) * TY + j) * TX + i;
+    }
+
+    // local coordinates of cross-region index ci; returns the halo direction
+    // (0,1,2) or -1 for a core cell
+    __host__ __device__ static inline int cdecode(int ci, int &i, int &j, int &k)
+    {
+        if (ci < T) {
+            i = ci % TX;
+            j = (ci / TX) % TY;
+            k = ci / (TX * TY);
+            return -1;
+        }
+        ci -= T;
+        if (ci < 2 * HX) {
+            int hi = ci >= HX;
+            if (hi) ci -= HX;
+            int r = ci / 3;
+            i = (ci % 3) + (hi ? TX : -3);
+            j = r % TY;
+            k = r / TY;
+            return 0;
+        }
+        ci -= 2 * HX;
+        if (ci < 2 * HY) {
+            int hi = ci >= HY;
+            if (hi) ci -= HY;
+            i = ci % TX;
+            int r = ci / TX;
+            j = (r % 3) + (hi ? TY : -3);
+            k = r / 3;
+            return 1;
+        }
+        ci -= 2 * HY;
+        int hi = ci >= HZ;
+        if (hi) ci -= HZ;
+        i = ci % TX;
+        j = (ci / TX) % TY;
+        k = (ci / (TX * TY)) + (hi ? TZ : -3);
+        return 2;
+    }
+};
+
+// RK combine: out = a * un + b * (uk + dt * L); a == 0 skips un.  RHS mode writes L.
+struct StageArgs {
+    const double *qk;   // u^(k): stencil source
+    const double *qn;   // u^n (own cell only), may equal qk or be null when a == 0
+    double *qo;         // output
+    const double *P;    // primitive scratch of qk
+    const double *dtp;  // device step (RK mode)
+    double a, b;
+    int rhs_mode;       // 1: write L instead of the combine
+    int sources;        // 0: leave bubble source terms out (split mode flux part)
+    int ntile[3];
+    int nblk_per_xcd;
+    int ntiles;
+};
+
+template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF>
+__global__ void __launch_bounds__(BLOCK) k_stage(StageArgs A, Grid g, Phys ph, Bins bins)
+{
+    using G = Geo<D, TX_, TY_, TZ_>;
+    constexpr int T = G::T, F = G::F, C = G::C, NC = G::NC, NCF = G::NCF, L = G::L;
+    constexpr int CPT = (C + BLOCK - 1) / BLOCK;  // cross cells staged per thread
+    constexpr int SCR = (NCF * F > 2 * L + 2 * F) ? NCF * F : 2 * L + 2 * F;
+    __shared__ TF s_coef[F];
+    __shared__ TF s_scr[SCR];
+    __shared__ unsigned char s_flag[F];
+
+    // XCD-aware tile order: consecutive tiles land on the same XCD (blocks are dealt round-robin).
+    const int b = blockIdx.x;
+    const int tile = (b & 7) * A.nblk_per_xcd + (b >> 3);
+    if (tile >= A.ntiles) return;
+    const int tx = tile % A.ntile[0];
+    const int ty = (tile / A.ntile[0]) % A.ntile[1];
+    const int tz = tile / (A.ntile[0] * A.ntile[1]);
+    const int x0 = tx * G::TX, y0 = ty * G::TY, z0 = tz * G::TZ;
+    const long long N = g.N;
+    const int nb = bins.nb;
+    const int tid = threadIdx.x;
+    const TF pinf = (TF)ph.pi_inf, gpi = (TF)ph.gpi, igm1 = (TF)ph.inv_gm1, gam = (TF)ph.gamma;
+
+    // ---- per-thread staging plan: global index, 1/n and line-array slots of its cross cells ----
+    unsigned st_g[CPT];
+    double st_in[CPT];
+    int st_l[CPT][D];
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+        int ci = tid + r * BLOCK;
+        st_g[r] = 0;
+        st_in[r] = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) st_l[r][d] = -1;
+        if (ci < C) {
+            int i, j, k;
+            int h = G::cdecode(ci, i, j, k);
+            bool f = false;
+            int gx = map_coord(x0 + i, g.n[0], g.bc[0], f);
+            int gy = D > 1 ? map_coord(y0 + j, g.n[1], g.bc[1], f) : 0;
+            int gz = D > 2 ? map_coord(z0 + k, g.n[2], g.bc[2], f) : 0;
+            unsigned gi = (unsigned)gx + (unsigned)g.n[0] * ((unsigned)gy + (unsigned)g.n[1] * (unsigned)gz);
+            st_g[r] = gi;
+            double n = A.P[PL<D>::N * N + gi];
+            st_in[r] = n > 0.0 ? frcp(n) : 0.0;
+            if (h == 0 || h < 0) st_l[r][0] = G::template lidx<0>(i, j, k);
+            if (D > 1 && (h == 1 || h < 0)) st_l[r][D > 1 ? 1 : 0] = G::template lidx<(D > 1 ? 1 : 0)>(i, j, k);
+            if (D > 2 && (h == 2 || h < 0)) st_l[r][D > 2 ? 2 : 0] = G::template lidx<(D > 2 ? 2 : 0)>(i, j, k);
+        }
+    }
+
+    // ---- core faces: WENO5 of the mixture primitives, HLLC ----
+    TF *s_cf = s_scr;  // [NCF][F]
+    auto core_faces = [&](auto dtag) {
+        constexpr int d = decltype(dtag)::value;
+        constexpr int BX = G::template BX<d>(), BY = G::template BY<d>();
+        constexpr int FD = (d == 0) ? G::FX : (d == 1 ? G::FY : G::FZ);
+        for (int t = tid; t < FD; t += BLOCK) {
+            int fi = t % BX, fj = (t / BX) % BY, fk = t / (BX * BY);
+            int lc[3] = {fi, fj, fk};
+            int org[3] = {x0, y0, z0};
+            // global index of the 6 cells along d (positions f-3 .. f+2)
+            unsigned gi6[6];
+            bool fl6[6];
+            {
+                bool fo = false;
+                int gt[3];
+#pragma unroll
+                for (int e = 0; e < 3; ++e)
+                    gt[e] = (e < D && e != d) ? map_coord(org[e] + lc[e], g.n[e], g.bc[e], fo) : 0;
+#pragma unroll
+                for (int o = 0; o < 6; ++o) {
+                    bool f = false;
+                    int gd = map_coord(org[d] + lc[d] - 3 + o, g.n[d], g.bc[d], f);
+                    int cc[3] = {gt[0], gt[1], gt[2]};
+                    cc[d] = gd;
+                    gi6[o] = (unsigned)cc[0] + (unsigned)g.n[0] * ((unsigned)cc[1] + (unsigned)g.n[1] * (unsigned)cc[2]);
+                    fl6[o] = f;
+                }
+            }
+            TF WL[NC], WR[NC], WcL[NC], WcR[NC];
+#pragma unroll
+            for (int v = 0; v < NC; ++v) {
+                TF s[6];
+#pragma unroll
+                for (int o = 0; o < 6; ++o) s[o] = (TF)A.P[(long long)v * N + gi6[o]];
+                if (v == 1 + d) {
+#pragma unroll
+                    for (int o = 0; o < 6; ++o) s[o] = fl6[o] ? -s[o] : s[o];
+                }
+                WL[v] = weno5(s[0], s[1], s[2], s[3], s[4]);
+                WR[v] = weno5(s[5], s[4], s[3], s[2], s[1]);
+                WcL[v] = s[2];
+                WcR[v] = s[3];
+            }
+            constexpr int iPL = D + 1, iA = D + 2, iN = D + 3, iB = D + 4;
+            bool ok = WL[0] > TF(0) && WR[0] > TF(0) && WL[iA] >= TF(0) && WL[iA] < TF(1) && WR[iA] >= TF(0) &&
+                      WR[iA] < TF(1) && WL[iN] >= TF(0) && WR[iN] >= TF(0) && WL[iPL] + pinf > TF(0) &&
+                      WR[iPL] + pinf > TF(0);
+            if (!ok) {
+#pragma unroll
+                for (int v = 0; v < NC; ++v) {
+                    WL[v] = WcL[v];
+                    WR[v] = WcR[v];
+                }
+            }
+            // HLLC (Davis speeds, Toro contact speed, difference-form star flux)
+            TF pK[2], EK[2], cK[2];
+            const TF *Ws[2] = {WL, WR};
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const TF *Wk = Ws[s];
+                TF a = Wk[iA], oma = TF(1) - a;
+                TF u2 = TF(0);
+#pragma unroll
+                for (int e = 0; e < D; ++e) u2 += Wk[1 + e] * Wk[1 + e];
+                pK[s] = oma * Wk[iPL] + a * Wk[iB];
+                EK[s] = oma * (Wk[iPL] + gpi) * igm1 + TF(0.5) * Wk[0] * u2;
+                cK[s] = tsqrt(gam * (Wk[iPL] + pinf) * oma * trcp(Wk[0]));
+            }
+            TF uL = WL[1 + d], uR = WR[1 + d];
+            TF SL = dmin(uL - cK[0], uR - cK[1]);
+            TF SR = dmax(uL + cK[0], uR + cK[1]);
+            TF mL = WL[0] * (SL - uL), mR = WR[0] * (SR - uR);
+            TF Ss = tdiv(pK[1] - pK[0] + uL * mL - uR * mR, mL - mR);
+            int side, star;
+            if (SL >= TF(0)) { side = 0; star = 0; }
+            else if (Ss >= TF(0)) { side = 0; star = 1; }
+            else if (SR > TF(0)) { side = 1; star = 1; }
+            else { side = 1; star = 0; }
+            const TF *WK = side ? WR : WL;
+            TF SK = side ? SR : SL;
+            TF un = WK[1 + d], rk = WK[0], pk = side ? pK[1] : pK[0], ek = side ? EK[1] : EK[0];
+            TF fac = star ? tdiv(SK * (Ss - un), SK - Ss) : TF(0);
+            TF F_[NCF];
+            F_[0] = rk * un + fac * rk;
+#pragma unroll
+            for (int e = 0; e < D; ++e)
+                F_[1 + e] = rk * un * WK[1 + e] + (e == d ? pk : TF(0)) + fac * rk * (e == d ? SK : WK[1 + e]);
+            F_[D + 1] = (ek + pk) * un + fac * (ek + pk + rk * Ss * (SK - un));
+            F_[D + 2] = WK[iA] * un + fac * WK[iA];
+            const int slot = G::OFF[d] + t;
+#pragma unroll
+            for (int v = 0; v < NCF; ++v) s_cf[v * F + slot] = F_[v];
+            // passive bin flux = coef * phi_K with coef = n_K (u_K + fac)
+            s_coef[slot] = WK[iN] * (un + fac);
+            s_flag[slot] = (unsigned char)(side | (ok ? 0 : 2));
+        }
+    };
+    core_faces(std::integral_constant<int, 0>{});
+    if (D > 1) core_faces(std::integral_constant<int, (D > 1 ? 1 : 0)>{});
+    if (D > 2) core_faces(std::integral_constant<int, (D > 2 ? 2 : 0)>{});
+
+    // first bin's global loads go out while the core faces finish
+    const int iNR = D + 3, iNV = D + 3 + nb;
+    double pre_r[CPT], pre_v[CPT];
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+        bool ok = tid + r * BLOCK < C;
+        pre_r[r] = ok ? A.qk[(long long)iNR * N + st_g[r]] : 0.0;
+        pre_v[r] = ok ? A.qk[(long long)iNV * N + st_g[r]] : 0.0;
+    }
+    __syncthreads();
+
+    // ---- own cell: core divergence, sources, RK combine ----
+    const bool own = tid < T;
+    int ci_ = own ? tid : 0;
+    int li = ci_ % G::TX, lj = (ci_ / G::TX) % G::TY, lk = ci_ / (G::TX * G::TY);
+    const bool active = own && (x0 + li < g.n[0]) && (D < 2 || y0 + lj < g.n[1]) && (D < 3 || z0 + lk < g.n[2]);
+    const long long gc = (long long)(x0 + li) + (long long)g.n[0] * ((long long)(y0 + lj) + (long long)g.n[1] * (z0 + lk));
+    int flo[3], fhi[3];
+    {
+        // face slots of the own cell: lo face has the cell's coordinate, hi face +1 along d
+        flo[0] = G::OFF[0] + li + (G::TX + 1) * (lj + G::TY * lk);
+        fhi[0] = flo[0] + 1;
+        flo[1] = D > 1 ? G::OFF[1] + li + G::TX * (lj + (G::TY + 1) * lk) : 0;
+        fhi[1] = flo[1] + G::TX;
+        flo[2] = D > 2 ? G::OFF[2] + li + G::TX * (lj + G::TY * lk) : 0;
+        fhi[2] = flo[2] + G::TX * G::TY;
+    }
+    const double dt = A.rhs_mode ? 0.0 : *A.dtp;
+    double own_n = 0.0, own_in = 0.0, own_pl = 0.0, own_irhol = 1.0, own_ic = 1.0;
+    if (active) {
+        TF Lc[NCF];
+#pragma unroll
+        for (int v = 0; v < NCF; ++v) {
+            TF acc = TF(0);
+#pragma unroll
+            for (int d = 0; d < D; ++d) acc += (s_cf[v * F + flo[d]] - s_cf[v * F + fhi[d]]) * (TF)g.inv_dx[d];
+            Lc[v] = acc;
+        }
+#pragma unroll
+        for (int v = 0; v < NCF; ++v) {
+            long long o = (long long)v * N + gc;
+            double Lv = (double)Lc[v];
+            if (v == D + 2 && A.sources) Lv += A.P[PL<D>::SA * N + gc];
+            if (A.rhs_mode) A.qo[o] = Lv;
+            else {
+                double r = A.b * (A.qk[o] + dt * Lv);
+                if (A.a != 0.0) r += A.a * A.qn[o];
+                A.qo[o] = r;
+            }
+        }
+        own_n = A.P[PL<D>::N * N + gc];
+        own_in = own_n > 0.0 ? frcp(own_n) : 0.0;
+        own_pl = A.P[PL<D>::PLQ * N + gc];
+        double a = A.P[PL<D>::A * N + gc];
+        double rhol = A.P[PL<D>::RHO * N + gc] / (1.0 - a);
+        own_irhol = frcp(rhol);
+        own_ic = frcp(sqrt(ph.gamma * (own_pl + ph.pi_inf) * own_irhol));
+    }
+    __syncthreads();  // s_cf is reused below
+
+    // ---- bins, one at a time: stage -> faces -> cells; next bin's loads overlap the faces ----
+    TF *s_R = s_scr, *s_V = s_scr + L, *s_fR = s_scr + 2 * L, *s_fV = s_scr + 2 * L + F;
+    for (int ib = 0; ib < nb; ++ib) {
+        const double r0 = bins.r0[ib];
+#pragma unroll
+        for (int r = 0; r < CPT; ++r) {
+            if (tid + r * BLOCK < C) {
+                double in = st_in[r];
+                TF Rv = (TF)(in > 0.0 ? pre_r[r] * in : r0);
+                TF Vv = (TF)(in > 0.0 ? pre_v[r] * in : 0.0);
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    int l = st_l[r][d];
+                    if (l >= 0) {
+                        s_R[l] = Rv;
+                        s_V[l] = Vv;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (ib + 1 < nb) {
+#pragma unroll
+            for (int r = 0; r < CPT; ++r) {
+                bool ok = tid + r * BLOCK < C;
+                pre_r[r] = ok ? A.qk[(long long)(iNR + ib + 1) * N + st_g[r]] : 0.0;
+                pre_v[r] = ok ? A.qk[(long long)(iNV + ib + 1) * N + st_g[r]] : 0.0;
+            }
+        }
+        auto bin_faces = [&](auto dtag) {
+            constexpr int d = decltype(dtag)::value;
+            constexpr int BX = G::template BX<d>(), BY = G::template BY<d>();
+            constexpr int FD = (d == 0) ? G::FX : (d == 1 ? G::FY : G::FZ);
+            constexpr int S = G::LSTRIDE[d];
+            for (int t = tid; t < FD; t += BLOCK) {
+                int fi = t % BX, fj = (t / BX) % BY, fk = t / (BX * BY);
+                const int slot = G::OFF[d] + t;
+                unsigned fl = s_flag[slot];
+                bool right = fl & 1;
+                // cells f-3 .. f+2 along d start at the face's own coordinates in the line array
+                int p[3] = {fi, fj, fk};
+                p[d] -= 3;
+                const int base = G::template lidx<d>(p[0], p[1], p[2]);
+                TF r6[6], v6[6];
+#pragma unroll
+                for (int o = 0; o < 6; ++o) {
+                    r6[o] = s_R[base + o * S];
+                    v6[o] = s_V[base + o * S];
+                }
+                // upwind side: L uses cells f-3..f+1, R the mirrored f+2..f-2
+                TF rr[5], vv[5];
+#pragma unroll
+                for (int o = 0; o < 5; ++o) {
+                    rr[o] = right ? r6[5 - o] : r6[o];
+                    vv[o] = right ? v6[5 - o] : v6[o];
+                }
+                TF RK, VK;
+                if (fl & 2) {
+                    RK = rr[2];
+                    VK = vv[2];
+                } else {
+                    RK = weno5(rr[0], rr[1], rr[2], rr[3], rr[4]);
+                    VK = weno5(vv[0], vv[1], vv[2], vv[3], vv[4]);
+                    if (!(RK > TF(0))) {
+                        RK = rr[2];
+                        VK = vv[2];
+                    }
+                }
+                TF cf = s_coef[slot];
+                s_fR[slot] = cf * RK;
+                s_fV[slot] = cf * VK;
+            }
+        };
+        bin_faces(std::integral_constant<int, 0>{});
+        if (D > 1) bin_faces(std::integral_constant<int, (D > 1 ? 1 : 0)>{});
+        if (D > 2) bin_faces(std::integral_constant<int, (D > 2 ? 2 : 0)>{});
+        __syncthreads();
+        if (active) {
+            TF LRf = TF(0), LVf = TF(0);
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                LRf += (s_fR[flo[d]] - s_fR[fhi[d]]) * (TF)g.inv_dx[d];
+                LVf += (s_fV[flo[d]] - s_fV[fhi[d]]) * (TF)g.inv_dx[d];
+            }
+            double LR = (double)LRf, LV = (double)LVf;
+            long long oR = (long long)(iNR + ib) * N + gc, oV = (long long)(iNV + ib) * N + gc;
+            const double xr0 = A.qk[oR], xv0 = A.qk[oV];
+            if (A.sources && own_n > 0.0) {
+                // Keller--Miksis in FP64 from the FP64 state of the owned cell
+                double own_R = xr0 * own_in, own_V = xv0 * own_in;
+                LR += own_n * own_V;
+                LV += own_n * km_rddot(ph, own_R, own_V, r0, bins.pg0[ib], own_pl, own_irhol, own_ic);
+            }
+            if (A.rhs_mode) {
+                A.qo[oR] = LR;
+                A.qo[oV] = LV;
+            } else {
+                double xr = A.b * (xr0 + dt * LR);
+                double xv = A.b * (xv0 + dt * LV);
+                if (A.a != 0.0) {
+                    xr += A.a * A.qn[oR];
+                    xv += A.a * A.qn[oV];
+                }
+                A.qo[oR] = xr;
+                A.qo[oV] = xv;
+            }
+        }
+        // the next bin's staging writes s_R/s_V only after every thread passed the barrier above,
+        // and s_fR/s_fV are rewritten only after the next staging barrier.
+    }
+}
+
+}  // namespace bub

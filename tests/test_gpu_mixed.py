@@ -1,0 +1,121 @@
+"""Mixed-precision form (FP32 reconstruction, Riemann solver and flux differences;
+FP64 primitives, moments, Keller--Miksis and RK accumulation) against FP64.
+
+The bar is the stated one: max-norm error of the liquid pressure, the mixture
+pressure and the void fraction relative to the field's max norm, at most 1e-5
+against the FP64 oracle.  The bin radii are reported.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.parity import flux_scale, perturb_bins, rel_err, rhs_err
+
+pytestmark = pytest.mark.gpu
+TOL_P_ALPHA = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    t = pytest.importorskip("torch")
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def bub(torch):
+    import paper_2511_21031_amd as B
+    B.lib()
+    return B
+
+
+def _gpu(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _field_errors(orc, pb, got, ref):
+    mg, mr = orc.moments(pb, got), orc.moments(pb, ref)
+    nd, nb = pb.ndim, pb.nb
+    Rg = got[nd + 3:nd + 3 + nb] / np.maximum(mg[0], 1e-300)
+    Rr = ref[nd + 3:nd + 3 + nb] / np.maximum(mr[0], 1e-300)
+    return {"p_l": rel_err(mg[7], mr[7]), "p": rel_err(mg[6], mr[6]), "alpha": rel_err(mg[1], mr[1]),
+            "R": float(np.abs(Rg - Rr).max() / np.abs(Rr).max())}
+
+
+@pytest.mark.parametrize("kind", ["c1", "2d", "3d"])
+def test_mixed_rhs(torch, bub, orc, kind):
+    case = {"c1": W.c1(), "2d": W.random_smooth(2, (70, 37), 1e-4, 5, seed=41),
+            "3d": W.random_smooth(3, (20, 13, 11), 1e-4, 3, seed=42, bc=1)}[kind]
+    pb = orc.problem_from_case(case)
+    q = perturb_bins(orc.init_state(pb, case.prim), case.ndim, case.nb, seed=5)
+    ref = orc.rhs(pb, q)
+    ctx = bub.context_from_case(case, precision=bub.PREC_MIXED)
+    got = ctx.rhs_stage(_gpu(torch, q)).cpu().numpy()
+    err = rhs_err(got, ref, flux_scale(orc, pb, q))
+    print(kind, "mixed RHS err (flux scale)", err.max())
+    assert err.max() < 1e-6
+
+
+def _trajectory(torch, bub, orc, case, steps, split=0):
+    pb = orc.problem_from_case(case, split=split)
+    q_ref = orc.init_state(pb, case.prim)
+    ctx = bub.context_from_case(case, precision=bub.PREC_MIXED,
+                                bubble_mode=bub.BUBBLES_SPLIT if split else bub.BUBBLES_UNSPLIT)
+    q = ctx.init_state(_gpu(torch, case.prim))
+    work = ctx.new_work()
+    for _ in range(steps):
+        dt = orc.cfl_dt(pb, q_ref)
+        orc.rk3_step(pb, q_ref, dt)
+        ctx.rk3_step(q, work, dt)
+    assert ctx.last_error()[0] == 0
+    return _field_errors(orc, pb, q.cpu().numpy(), q_ref)
+
+
+def test_mixed_c1_full_trajectory(torch, bub, orc):
+    e = _trajectory(torch, bub, orc, W.c1(), 200)
+    print("c1 mixed vs FP64 oracle, 200 steps:", e)
+    assert max(e["p_l"], e["p"], e["alpha"]) < TOL_P_ALPHA
+
+
+def test_mixed_2d_plane_wave(torch, bub, orc):
+    e = _trajectory(torch, bub, orc, W.c2(n=64, nb=11), 30)
+    print("2D mixed vs FP64 oracle, 30 steps:", e)
+    assert max(e["p_l"], e["p"], e["alpha"]) < TOL_P_ALPHA
+
+
+def test_mixed_3d_collapse_split(torch, bub, orc):
+    e = _trajectory(torch, bub, orc, W.c3(n=24, nb=5, width=6e-4), 8, split=1)
+    print("3D split mixed vs FP64 oracle, 8 steps:", e)
+    assert max(e["p_l"], e["p"], e["alpha"]) < TOL_P_ALPHA
+
+
+def test_mixed_vs_fp64_full_3d_crop(torch, bub):
+    """256^3, 21 bins, 10 atm pulse, split mode: mixed against plain FP64 on the GPU, central 64^3 crop."""
+    case = W.c3()
+    prim = _gpu(torch, case.prim)
+    out = {}
+    for prec in (bub.PREC_FP64, bub.PREC_MIXED):
+        ctx = bub.context_from_case(case, precision=prec, bubble_mode=bub.BUBBLES_SPLIT)
+        q = ctx.init_state(prim)
+        work = ctx.new_work()
+        for _ in range(3):
+            ctx.rk3_step(q, work)
+        assert ctx.last_error()[0] == 0
+        m = ctx.moments(q)
+        n = 256
+        sl = slice(96, 160)
+        Q = q.view(q.shape[0], n, n, n)[:, sl, sl, sl].cpu().numpy().reshape(q.shape[0], -1)
+        M = m.view(8, n, n, n)[:, sl, sl, sl].cpu().numpy().reshape(8, -1)
+        out[prec] = (Q, M)
+        del q, work, m, ctx
+        torch.cuda.empty_cache()
+    (Q64, M64), (Qm, Mm) = out[bub.PREC_FP64], out[bub.PREC_MIXED]
+    e_p = rel_err(Mm[6], M64[6])
+    e_pl = rel_err(Mm[7], M64[7])
+    e_a = rel_err(Mm[1], M64[1])
+    R64 = Q64[6:6 + 21] / M64[0]
+    Rm = Qm[6:6 + 21] / Mm[0]
+    e_R = float(np.abs(Rm - R64).max() / np.abs(R64).max())
+    print(f"256^3 split, 3 steps, 64^3 crop: mixed vs FP64 p {e_p:.2e} p_l {e_pl:.2e} alpha {e_a:.2e} R {e_R:.2e}")
+    assert max(e_p, e_pl, e_a) < TOL_P_ALPHA

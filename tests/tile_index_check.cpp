@@ -12,7 +12,7 @@
 #include <set>
 #include <tuple>
 
-#include "ee_kernels.hpp"
+#include "stage_kernel.hpp"
 
 using namespace bub;
 
