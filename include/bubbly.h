@@ -148,6 +148,54 @@ int bub_moments(bub_ctx *ctx, const double *q, double *out, void *stream);
  * of every (cell, bin).  Valid in either bubble mode. */
 int bub_bubble_advance(bub_ctx *ctx, double *q, double tau, int32_t *nsub, void *stream);
 
+/* ---- Volume-averaged (Euler--Lagrange) variant, Sec. 2.1 --------------------
+ * Needs a 3D context with equal spacing in all directions; its bins are not
+ * used.  Liquid state ql[5][N] = rho_l, rho_l u, rho_l v, rho_l w, E_l (device)
+ * with E_l = (p_l + gamma pi_inf)/(gamma-1) + rho_l |u|^2 / 2.  Bubbles are a
+ * device structure-of-arrays bubbles[8][nbub] = x, y, z, R0, R, Rdot, p_g0,
+ * h_sub (h_sub: last sub-step, carried between calls; 0 = none yet).  Bubbles
+ * are fixed in space (Sec. 2.1).  alpha_D[2][N] (device) holds the smeared void
+ * fraction alpha = sum V_n delta_n and its rate D = sum 4 pi R_n^2 Rdot_n delta_n,
+ * delta the Gaussian of eq. kernel3D with width h = max(dx, R_n) truncated at
+ * 3h (eq. model_inequality and the width rule after it), evaluated at cell
+ * centres; cells beyond a reflective wall are skipped, periodic ones wrap. */
+
+/* Bytes of the `work` buffer bub_lagrangian_step needs for nbub bubbles. */
+int bub_lagrangian_layout(const bub_ctx *ctx, int64_t nbub, size_t *work_bytes);
+
+/* Bubble records at rest at their equilibrium radius from xyzr0[4][nbub] =
+ * x, y, z, R0 (device): R = R0, Rdot = 0, p_g0 = p0 + 2 sigma/R0 - pv, h_sub = 0. */
+int bub_lagrangian_bubbles(bub_ctx *ctx, const double *xyzr0, double *bubbles, int64_t nbub, void *stream);
+
+/* Liquid conserved state from primitives prim[5][N] = rho_l, u, v, w, p_l (device). */
+int bub_lagrangian_init(bub_ctx *ctx, const double *prim, double *ql, void *stream);
+
+/* alpha_D <- smear of the bubbles (FP64 atomic adds: the summation order, and so
+ * the last bits, may differ between runs). */
+int bub_lagrangian_smear(bub_ctx *ctx, const double *bubbles, int64_t nbub, double *alpha_D, void *stream);
+
+/* Forcing of each bubble, out[3][nbub] (device): kernel-weighted liquid pressure
+ * sum(delta p_l)/sum(delta) over the support, and rho_l, c of the host cell. */
+int bub_lagrangian_gather(bub_ctx *ctx, const double *ql, const double *bubbles, int64_t nbub, double *out,
+                          void *stream);
+
+/* Liquid right-hand side (Sec. 2.1 liquid equations, inviscid) for frozen
+ * alpha_D: WENO5 + HLLC fluxes of the stiffened-gas liquid plus the sources
+ * rho_l D/(1-alpha), rho_l u D/(1-alpha) - alpha grad p_l/(1-alpha),
+ * E_l D/(1-alpha) - alpha div(p_l u)/(1-alpha), with grad p_l and div(p_l u)
+ * from face averages of the reconstructed states.  rhs[5][N] (device). */
+int bub_lagrangian_rhs(bub_ctx *ctx, const double *ql, const double *alpha_D, double *rhs, void *stream);
+
+/* One Strang-split step (lagrangian_step): bubbles over dt/2 (Keller--Miksis per
+ * bubble with adaptive Dormand--Prince 5(4), relative tolerance opts.sub_rtol,
+ * forcing gathered at the start and frozen), smear, liquid SSP-RK3 over dt with
+ * alpha_D frozen, bubbles over dt/2, smear.  dt <= 0: CFL step of the liquid.
+ * work: device buffer of bub_lagrangian_layout bytes.  dt_dev (device, may be
+ * NULL) receives the step; nsub (device int32 [nbub], may be NULL) the accepted
+ * sub-steps of each bubble over the step. */
+int bub_lagrangian_step(bub_ctx *ctx, double *ql, double *bubbles, int64_t nbub, double *alpha_D, double *work,
+                        double dt, double *dt_dev, int32_t *nsub, void *stream);
+
 /* Synchronises `stream`, then reports and clears the sticky device error word:
  * *code (BUB_OK or a device BUB_E* code), *cell (first failing cell or -1),
  * *bin (failing bin or -1).  Any output pointer may be NULL. */

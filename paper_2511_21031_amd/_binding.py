@@ -65,6 +65,13 @@ _SIGS = {
     "bub_last_error": [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_int),
                        _vp],
     "bub_bubble_advance": [_vp, _vp, ctypes.c_double, _vp, _vp],
+    "bub_lagrangian_layout": [_vp, _i64, ctypes.POINTER(ctypes.c_size_t)],
+    "bub_lagrangian_bubbles": [_vp, _vp, _vp, _i64, _vp],
+    "bub_lagrangian_init": [_vp, _vp, _vp, _vp],
+    "bub_lagrangian_smear": [_vp, _vp, _i64, _vp, _vp],
+    "bub_lagrangian_gather": [_vp, _vp, _vp, _i64, _vp, _vp],
+    "bub_lagrangian_rhs": [_vp, _vp, _vp, _vp, _vp],
+    "bub_lagrangian_step": [_vp, _vp, _vp, _i64, _vp, _vp, ctypes.c_double, _vp, _vp, _vp],
     "bub_tile_count": [_vp, ctypes.POINTER(ctypes.c_int)],
     "bub_tile_info": [_vp, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4,
     "bub_tile_set": [_vp, ctypes.c_int],
@@ -215,6 +222,49 @@ class Context:
         _check(lib().bub_bubble_advance(self._h, _ptr(q), float(tau),
                                         None if nsub is None else _vp(nsub.data_ptr()), _stream(stream)),
                "bub_bubble_advance")
+
+    # -- volume-averaged (Euler--Lagrange) variant ------------------------------
+    def lagrangian_work(self, nbub: int, device="cuda"):
+        wb = ctypes.c_size_t()
+        _check(lib().bub_lagrangian_layout(self._h, int(nbub), ctypes.byref(wb)), "bub_lagrangian_layout")
+        return torch.empty((wb.value // 8,), dtype=torch.float64, device=device)
+
+    def lagrangian_bubbles(self, xyzr0: torch.Tensor, stream=None):
+        """Bubble records [8][nbub] at rest at R0 from [4][nbub] = x, y, z, R0."""
+        nb = xyzr0.shape[1]
+        out = torch.empty((8, nb), dtype=torch.float64, device=xyzr0.device)
+        _check(lib().bub_lagrangian_bubbles(self._h, _ptr(xyzr0), _ptr(out), nb, _stream(stream)),
+               "bub_lagrangian_bubbles")
+        return out
+
+    def lagrangian_init(self, prim: torch.Tensor, stream=None):
+        ql = torch.empty((5, self.ncells), dtype=torch.float64, device=prim.device)
+        _check(lib().bub_lagrangian_init(self._h, _ptr(prim), _ptr(ql), _stream(stream)), "bub_lagrangian_init")
+        return ql
+
+    def lagrangian_smear(self, bubbles: torch.Tensor, alpha_D: torch.Tensor | None = None, stream=None):
+        aD = torch.empty((2, self.ncells), dtype=torch.float64, device=bubbles.device) if alpha_D is None else alpha_D
+        _check(lib().bub_lagrangian_smear(self._h, _ptr(bubbles), bubbles.shape[1], _ptr(aD), _stream(stream)),
+               "bub_lagrangian_smear")
+        return aD
+
+    def lagrangian_gather(self, ql: torch.Tensor, bubbles: torch.Tensor, stream=None):
+        out = torch.empty((3, bubbles.shape[1]), dtype=torch.float64, device=ql.device)
+        _check(lib().bub_lagrangian_gather(self._h, _ptr(ql), _ptr(bubbles), bubbles.shape[1], _ptr(out),
+                                           _stream(stream)), "bub_lagrangian_gather")
+        return out
+
+    def lagrangian_rhs(self, ql: torch.Tensor, alpha_D: torch.Tensor, stream=None):
+        rhs = torch.empty_like(ql)
+        _check(lib().bub_lagrangian_rhs(self._h, _ptr(ql), _ptr(alpha_D), _ptr(rhs), _stream(stream)),
+               "bub_lagrangian_rhs")
+        return rhs
+
+    def lagrangian_step(self, ql, bubbles, alpha_D, work, dt=0.0, dt_dev=None, nsub=None, stream=None):
+        _check(lib().bub_lagrangian_step(self._h, _ptr(ql), _ptr(bubbles), bubbles.shape[1], _ptr(alpha_D),
+                                         _ptr(work), float(dt), _ptr(dt_dev),
+                                         None if nsub is None else _vp(nsub.data_ptr()), _stream(stream)),
+               "bub_lagrangian_step")
 
     def tiles(self):
         """List of (tx, ty, tz, block) stage-kernel tile shapes for this dimensionality."""

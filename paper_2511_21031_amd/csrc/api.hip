@@ -13,6 +13,7 @@
 #include "ee_kernels.hpp"
 #include "split_kernels.hpp"
 #include "stage_kernel.hpp"
+#include "el_kernels.hpp"
 #include "ctx.hpp"
 
 using namespace bub;
@@ -418,6 +419,196 @@ int bub_rk3_step(bub_ctx *c, double *q, double *work, double dt, double *dt_dev,
     if ((rc = stage(c, A, s))) return rc;
     if (split) rc = bubble(c, q, &c->d_sc->dt, 0.5, 0.0, nullptr, s);   // S_b(dt/2)
     return rc;
+}
+
+// ---------------------------------------------------------------------------
+// Volume-averaged (Euler--Lagrange) variant
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+int el_grid(const bub_ctx *c, ElGrid *g)
+{
+    if (c->ndim != 3) return BUB_EUNSUPPORTED;
+    if (c->grid.dx[1] != c->grid.dx[0] || c->grid.dx[2] != c->grid.dx[0]) return BUB_EUNSUPPORTED;
+    for (int d = 0; d < 3; ++d) {
+        g->n[d] = c->g.n[d];
+        g->bc[d] = c->g.bc[d];
+        if (g->n[d] < 3) return BUB_EUNSUPPORTED;
+    }
+    g->dx = c->grid.dx[0];
+    g->inv_dx = 1.0 / g->dx;
+    g->N = c->N;
+    return BUB_OK;
+}
+
+int el_prim(bub_ctx *c, const ElGrid &g, const double *ql, bool cfl, hipStream_t s)
+{
+    long pr = prof_begin(c, BUB_K_PRIM, s);
+    if (cfl)
+        hipLaunchKernelGGL((k_el_prim<true>), dim3(blocks_for(g.N)), dim3(256), 0, s, ql, c->d_P, g, c->ph, c->d_sc);
+    else
+        hipLaunchKernelGGL((k_el_prim<false>), dim3(blocks_for(g.N)), dim3(256), 0, s, ql, c->d_P, g, c->ph, c->d_sc);
+    prof_end(c, pr, s);
+    return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
+}
+
+int el_smear(bub_ctx *c, const ElGrid &g, const double *b, long long nb, double *aD, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(2 * g.N)), dim3(256), 0, s, aD, 2 * g.N, 0.0);
+    if (nb > 0) {
+        long pr = prof_begin(c, BUB_K_OTHER, s);
+        hipLaunchKernelGGL(k_el_scatter, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s, b, nb, g, aD);
+        prof_end(c, pr, s);
+    }
+    return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
+}
+
+// gather from the primitives in c->d_P, then advance every bubble over (*taup) * scale
+int el_bubbles(bub_ctx *c, const ElGrid &g, double *b, long long nb, double *forcing, const double *taup,
+               double scale, int *nsub, hipStream_t s)
+{
+    if (nb <= 0) return BUB_OK;
+    long pr = prof_begin(c, BUB_K_OTHER, s);
+    hipLaunchKernelGGL(k_el_gather, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s, c->d_P, b, nb, g, c->ph, forcing);
+    ElOdeArgs O{};
+    O.b = b;
+    O.nb = nb;
+    O.forcing = forcing;
+    O.taup = taup;
+    O.tau_scale = scale;
+    O.rtol = c->opts.sub_rtol > 0.0 ? c->opts.sub_rtol : 1e-4;
+    O.max_substeps = c->opts.max_substeps > 0 ? c->opts.max_substeps : 10000;
+    O.nsub = nsub;
+    hipLaunchKernelGGL(k_el_ode, dim3(blocks_for(nb)), dim3(256), 0, s, O, c->ph, c->d_sc);
+    prof_end(c, pr, s);
+    return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
+}
+
+int el_stage(bub_ctx *c, const ElGrid &g, ElStageArgs A, hipStream_t s)
+{
+    long pr = prof_begin(c, BUB_K_STAGE, s);
+    hipLaunchKernelGGL(k_el_stage, dim3(blocks_for(g.N)), dim3(256), 0, s, A, g, c->ph);
+    prof_end(c, pr, s);
+    return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
+}
+
+__global__ void k_fill_i(int *p, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bub_lagrangian_layout(const bub_ctx *c, int64_t nbub, size_t *work_bytes)
+{
+    ElGrid g;
+    if (!c || !work_bytes || nbub < 0) return BUB_EINVAL;
+    int rc = el_grid(c, &g);
+    if (rc) return rc;
+    *work_bytes = sizeof(double) * (size_t)(10 * g.N + 3 * nbub);
+    return BUB_OK;
+}
+
+int bub_lagrangian_bubbles(bub_ctx *c, const double *xyzr0, double *bubbles, int64_t nbub, void *stream)
+{
+    ElGrid g;
+    if (!c || nbub < 0 || (nbub > 0 && (!xyzr0 || !bubbles))) return BUB_EINVAL;
+    int rc = el_grid(c, &g);
+    if (rc || nbub == 0) return rc;
+    hipLaunchKernelGGL(k_el_bubinit, dim3(blocks_for(nbub)), dim3(256), 0, (hipStream_t)stream, xyzr0, bubbles,
+                       (long long)nbub, c->ph, 2.0 * c->gas.sigma, c->gas.pv);
+    return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
+}
+
+int bub_lagrangian_init(bub_ctx *c, const double *prim_in, double *ql, void *stream)
+{
+    ElGrid g;
+    if (!c || !prim_in || !ql) return BUB_EINVAL;
+    int rc = el_grid(c, &g);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_el_init, dim3(blocks_for(g.N)), dim3(256), 0, (hipStream_t)stream, prim_in, ql, g.N, c->ph);
+    return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
+}
+
+int bub_lagrangian_smear(bub_ctx *c, const double *bubbles, int64_t nbub, double *alpha_D, void *stream)
+{
+    ElGrid g;
+    if (!c || !alpha_D || nbub < 0 || (nbub > 0 && !bubbles)) return BUB_EINVAL;
+    int rc = el_grid(c, &g);
+    if (rc) return rc;
+    return el_smear(c, g, bubbles, nbub, alpha_D, (hipStream_t)stream);
+}
+
+int bub_lagrangian_gather(bub_ctx *c, const double *ql, const double *bubbles, int64_t nbub, double *out,
+                          void *stream)
+{
+    ElGrid g;
+    if (!c || !ql || nbub < 0 || (nbub > 0 && (!bubbles || !out))) return BUB_EINVAL;
+    int rc = el_grid(c, &g);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = el_prim(c, g, ql, false, s))) return rc;
+    if (nbub > 0)
+        hipLaunchKernelGGL(k_el_gather, dim3((unsigned)((nbub + 3) / 4)), dim3(256), 0, s, c->d_P, bubbles,
+                           (long long)nbub, g, c->ph, out);
+    return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
+}
+
+int bub_lagrangian_rhs(bub_ctx *c, const double *ql, const double *alpha_D, double *rhs, void *stream)
+{
+    ElGrid g;
+    if (!c || !ql || !alpha_D || !rhs || ql == rhs) return BUB_EINVAL;
+    int rc = el_grid(c, &g);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = el_prim(c, g, ql, false, s))) return rc;
+    ElStageArgs A{};
+    A.qk = ql;
+    A.qo = rhs;
+    A.P = c->d_P;
+    A.aD = alpha_D;
+    A.b = 1.0;
+    A.rhs_mode = 1;
+    return el_stage(c, g, A, s);
+}
+
+int bub_lagrangian_step(bub_ctx *c, double *ql, double *bubbles, int64_t nbub, double *alpha_D, double *work,
+                        double dt, double *dt_dev, int32_t *nsub, void *stream)
+{
+    ElGrid g;
+    if (!c || !ql || !alpha_D || !work || nbub < 0 || (nbub > 0 && !bubbles)) return BUB_EINVAL;
+    if (!(dt == dt) || dt == INFINITY) return BUB_EINVAL;
+    int rc = el_grid(c, &g);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    double *w1 = work, *w2 = work + 5 * g.N, *forcing = work + 10 * g.N;
+    const bool cfl = !(dt > 0.0);
+    if ((rc = el_prim(c, g, ql, cfl, s))) return rc;
+    hipLaunchKernelGGL(k_dt, dim3(1), dim3(1), 0, s, c->d_sc, cfl ? 0.0 : dt, c->opts.cfl, dt_dev);
+    if (nsub && nbub > 0) hipLaunchKernelGGL(k_fill_i, dim3(blocks_for(nbub)), dim3(256), 0, s, nsub, (long long)nbub);
+    const double *dtp = &c->d_sc->dt;
+    if ((rc = el_bubbles(c, g, bubbles, nbub, forcing, dtp, 0.5, nsub, s))) return rc;
+    if ((rc = el_smear(c, g, bubbles, nbub, alpha_D, s))) return rc;
+    ElStageArgs A{};
+    A.P = c->d_P;
+    A.aD = alpha_D;
+    A.dtp = dtp;
+    A.qk = ql; A.qn = nullptr; A.qo = w1; A.a = 0.0; A.b = 1.0;          // P still holds the primitives of ql
+    if ((rc = el_stage(c, g, A, s))) return rc;
+    if ((rc = el_prim(c, g, w1, false, s))) return rc;
+    A.qk = w1; A.qn = ql; A.qo = w2; A.a = 0.75; A.b = 0.25;
+    if ((rc = el_stage(c, g, A, s))) return rc;
+    if ((rc = el_prim(c, g, w2, false, s))) return rc;
+    A.qk = w2; A.qn = ql; A.qo = ql; A.a = 1.0 / 3.0; A.b = 2.0 / 3.0;
+    if ((rc = el_stage(c, g, A, s))) return rc;
+    if ((rc = el_prim(c, g, ql, false, s))) return rc;
+    if ((rc = el_bubbles(c, g, bubbles, nbub, forcing, dtp, 0.5, nsub, s))) return rc;
+    return el_smear(c, g, bubbles, nbub, alpha_D, s);
 }
 
 int bub_bubble_advance(bub_ctx *c, double *q, double tau, int32_t *nsub, void *stream)

@@ -1,0 +1,406 @@
+// Volume-averaged (Euler--Lagrange) variant, Sec. 2.1, for gfx950.
+//
+//  k_el_bubinit  bubble records (x, y, z, R0) -> state at rest at R0.
+//  k_el_init     liquid primitives -> conserved liquid state.
+//  k_el_prim     liquid primitives (rho, u, v, w, p) per cell, optional CFL max.
+//  k_el_gather   one wavefront per bubble: kernel-weighted liquid pressure over
+//                the truncated Gaussian support (normalised), host-cell rho, c.
+//  k_el_ode      one thread per bubble: Keller--Miksis with adaptive
+//                Dormand--Prince 5(4) sub-steps, forcing frozen.
+//  k_el_scatter  one wavefront per bubble: volume and volume rate smeared with
+//                the kernel (eq. kernel3D) by FP64 atomic adds.
+//  k_el_stage    one thread per cell: WENO5 + HLLC fluxes of the liquid
+//                (stiffened gas), the bubble source terms with alpha and its
+//                rate frozen, RK combine.
+#pragma once
+
+#include <type_traits>
+
+#include "device_common.hpp"
+
+namespace bub {
+
+// bubble record slots
+enum { BX_ = 0, BY_ = 1, BZ_ = 2, BR0 = 3, BRR = 4, BRD = 5, BPG = 6, BHS = 7, NBREC = 8 };
+
+struct ElGrid {
+    int n[3];
+    int bc[3];
+    double dx, inv_dx;
+    long long N;
+};
+
+__device__ inline double el_kernel(double d2, double h)
+{
+    // truncated Gaussian of width h, support d < 3h
+    const double c = 0.063493635934240969;  // (2 pi)^(-3/2)
+    if (d2 >= 9.0 * h * h) return 0.0;
+    return c / (h * h * h) * exp(-0.5 * d2 / (h * h));
+}
+
+// stencil coordinate: periodic wrap, or -1 outside a reflective wall
+__device__ inline int el_wrap(int i, int n, int bc)
+{
+    if ((unsigned)i < (unsigned)n) return i;
+    if (bc != 0) return -1;
+    int m = i % n;
+    return m < 0 ? m + n : m;
+}
+
+__global__ void k_el_bubinit(const double *__restrict__ xyzr, double *__restrict__ b, long long nb, Phys ph,
+                             double sigma2, double pv)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (long long)gridDim.x * blockDim.x) {
+        double r0 = xyzr[3 * nb + i];
+        b[BX_ * nb + i] = xyzr[i];
+        b[BY_ * nb + i] = xyzr[nb + i];
+        b[BZ_ * nb + i] = xyzr[2 * nb + i];
+        b[BR0 * nb + i] = r0;
+        b[BRR * nb + i] = r0;
+        b[BRD * nb + i] = 0.0;
+        b[BPG * nb + i] = ph.p0 + sigma2 / r0 - pv;
+        b[BHS * nb + i] = 0.0;
+    }
+}
+
+__global__ void k_el_init(const double *__restrict__ prim, double *__restrict__ ql, long long N, Phys ph)
+{
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
+        double rho = prim[c], ke = 0.0;
+        ql[c] = rho;
+        for (int d = 0; d < 3; ++d) {
+            double u = prim[(1 + d) * N + c];
+            ql[(1 + d) * N + c] = rho * u;
+            ke += u * u;
+        }
+        ql[4 * N + c] = (prim[4 * N + c] + ph.gpi) * ph.inv_gm1 + 0.5 * rho * ke;
+    }
+}
+
+template <bool CFL>
+__global__ void __launch_bounds__(256) k_el_prim(const double *__restrict__ ql, double *__restrict__ P, ElGrid g,
+                                                 Phys ph, Scalars *sc)
+{
+    const long long N = g.N;
+    double wmax = 0.0;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
+        double rho = ql[c];
+        double ir = frcp(rho);
+        double u[3], ke = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            u[d] = ql[(1 + d) * N + c] * ir;
+            ke += u[d] * u[d];
+        }
+        double p = ph.gm1 * (ql[4 * N + c] - 0.5 * rho * ke) - ph.gpi;
+        P[c] = rho;
+        for (int d = 0; d < 3; ++d) P[(1 + d) * N + c] = u[d];
+        P[4 * N + c] = p;
+        if (!(rho > 0.0) || !(p + ph.pi_inf > 0.0)) raise_error(sc, E_NONFINITE, c, -1);
+        if (CFL) {
+            double cs = sqrt(ph.gamma * (p + ph.pi_inf) * ir);
+            for (int d = 0; d < 3; ++d) wmax = dmax(wmax, (fabs(u[d]) + cs) * g.inv_dx);
+        }
+    }
+    if (CFL) {
+        for (int off = 32; off > 0; off >>= 1) wmax = dmax(wmax, __shfl_xor(wmax, off, 64));
+        if ((threadIdx.x & 63) == 0 && wmax > 0.0)
+            atomicMax(&sc->wmax, (unsigned long long)__double_as_longlong(wmax));
+    }
+}
+
+// Host cell of a bubble coordinate and the kernel support half-width in cells.
+__device__ inline void el_support(const double *b, long long nb, long long i, const ElGrid &g, int host[3], double &h,
+                                  int &m)
+{
+    double R = b[BRR * nb + i];
+    h = dmax(g.dx, R);
+    m = (int)ceil(3.0 * h * g.inv_dx);
+    for (int d = 0; d < 3; ++d) host[d] = (int)floor(b[d * nb + i] * g.inv_dx);
+}
+
+// one wavefront (64 lanes) per bubble
+__global__ void __launch_bounds__(256) k_el_gather(const double *__restrict__ P, const double *__restrict__ b,
+                                                   long long nb, ElGrid g, Phys ph, double *__restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (i >= nb) return;
+    const long long N = g.N;
+    int host[3], m;
+    double h;
+    el_support(b, nb, i, g, host, h, m);
+    const double xb[3] = {b[BX_ * nb + i], b[BY_ * nb + i], b[BZ_ * nb + i]};
+    const int w = 2 * m + 1, tot = w * w * w;
+    double sw = 0.0, swp = 0.0;
+    for (int o = lane; o < tot; o += 64) {
+        int off[3] = {o % w - m, (o / w) % w - m, o / (w * w) - m};
+        int cc[3];
+        bool out_ = false;
+        double d2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            double xc = (host[d] + off[d] + 0.5) * g.dx;
+            d2 += (xc - xb[d]) * (xc - xb[d]);
+            cc[d] = el_wrap(host[d] + off[d], g.n[d], g.bc[d]);
+            if (cc[d] < 0) out_ = true;
+        }
+        if (out_) continue;
+        double wk = el_kernel(d2, h);
+        if (wk == 0.0) continue;
+        long long c = cc[0] + (long long)g.n[0] * (cc[1] + (long long)g.n[1] * cc[2]);
+        sw += wk;
+        swp += wk * P[4 * N + c];
+    }
+    for (int s = 32; s > 0; s >>= 1) {
+        sw += __shfl_xor(sw, s, 64);
+        swp += __shfl_xor(swp, s, 64);
+    }
+    if (lane == 0) {
+        int hc[3];
+        for (int d = 0; d < 3; ++d) {
+            hc[d] = el_wrap(host[d], g.n[d], g.bc[d]);
+            if (hc[d] < 0) hc[d] = host[d] < 0 ? 0 : g.n[d] - 1;
+        }
+        long long c = hc[0] + (long long)g.n[0] * (hc[1] + (long long)g.n[1] * hc[2]);
+        double rho = P[c], p = P[4 * N + c];
+        out[i] = swp / sw;
+        out[nb + i] = rho;
+        out[2 * nb + i] = sqrt(ph.gamma * (p + ph.pi_inf) / rho);
+    }
+}
+
+// Dormand--Prince 5(4) step of (R, Rdot) (published tableau, 1980).
+__device__ inline void dp54(const Phys &ph, double r0, double pg0, double pinf, double irho, double ic, double y0,
+                            double y1, double h, double &r5, double &v5, double &r4, double &v4)
+{
+    const double a21 = 1.0 / 5.0;
+    const double a31 = 3.0 / 40.0, a32 = 9.0 / 40.0;
+    const double a41 = 44.0 / 45.0, a42 = -56.0 / 15.0, a43 = 32.0 / 9.0;
+    const double a51 = 19372.0 / 6561.0, a52 = -25360.0 / 2187.0, a53 = 64448.0 / 6561.0, a54 = -212.0 / 729.0;
+    const double a61 = 9017.0 / 3168.0, a62 = -355.0 / 33.0, a63 = 46732.0 / 5247.0, a64 = 49.0 / 176.0,
+                 a65 = -5103.0 / 18656.0;
+    const double b1 = 35.0 / 384.0, b3 = 500.0 / 1113.0, b4 = 125.0 / 192.0, b5 = -2187.0 / 6784.0, b6 = 11.0 / 84.0;
+    const double e1 = 5179.0 / 57600.0, e3 = 7571.0 / 16695.0, e4 = 393.0 / 640.0, e5 = -92097.0 / 339200.0,
+                 e6 = 187.0 / 2100.0, e7 = 1.0 / 40.0;
+    auto f = [&](double R, double V) { return km_rddot(ph, R, V, r0, pg0, pinf, irho, ic); };
+    double k1r = y1, k1v = f(y0, y1);
+    double t0 = y0 + h * a21 * k1r, t1 = y1 + h * a21 * k1v;
+    double k2r = t1, k2v = f(t0, t1);
+    t0 = y0 + h * (a31 * k1r + a32 * k2r);
+    t1 = y1 + h * (a31 * k1v + a32 * k2v);
+    double k3r = t1, k3v = f(t0, t1);
+    t0 = y0 + h * (a41 * k1r + a42 * k2r + a43 * k3r);
+    t1 = y1 + h * (a41 * k1v + a42 * k2v + a43 * k3v);
+    double k4r = t1, k4v = f(t0, t1);
+    t0 = y0 + h * (a51 * k1r + a52 * k2r + a53 * k3r + a54 * k4r);
+    t1 = y1 + h * (a51 * k1v + a52 * k2v + a53 * k3v + a54 * k4v);
+    double k5r = t1, k5v = f(t0, t1);
+    t0 = y0 + h * (a61 * k1r + a62 * k2r + a63 * k3r + a64 * k4r + a65 * k5r);
+    t1 = y1 + h * (a61 * k1v + a62 * k2v + a63 * k3v + a64 * k4v + a65 * k5v);
+    double k6r = t1, k6v = f(t0, t1);
+    r5 = y0 + h * (b1 * k1r + b3 * k3r + b4 * k4r + b5 * k5r + b6 * k6r);
+    v5 = y1 + h * (b1 * k1v + b3 * k3v + b4 * k4v + b5 * k5v + b6 * k6v);
+    double k7r = v5, k7v = f(r5, v5);
+    r4 = y0 + h * (e1 * k1r + e3 * k3r + e4 * k4r + e5 * k5r + e6 * k6r + e7 * k7r);
+    v4 = y1 + h * (e1 * k1v + e3 * k3v + e4 * k4v + e5 * k5v + e6 * k6v + e7 * k7v);
+}
+
+struct ElOdeArgs {
+    double *b;
+    long long nb;
+    const double *forcing;  // [3][nb]: p_inf, rho_l, c_l
+    const double *taup;     // tau = *taup * tau_scale
+    double tau_scale;
+    double rtol;
+    int max_substeps;
+    int *nsub;              // accumulated accepted sub-steps per bubble, or null
+};
+
+__global__ void __launch_bounds__(256) k_el_ode(ElOdeArgs A, Phys ph, Scalars *sc)
+{
+    const long long nb = A.nb;
+    const double tau = *A.taup * A.tau_scale;
+    const double vfloor = 1e-3 * sqrt(ph.p0 / ph.rho0);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (long long)gridDim.x * blockDim.x) {
+        double *b = A.b;
+        const double r0 = b[BR0 * nb + i], pg0 = b[BPG * nb + i];
+        const double pinf = A.forcing[i], irho = frcp(A.forcing[nb + i]), ic = frcp(A.forcing[2 * nb + i]);
+        double y0 = b[BRR * nb + i], y1 = b[BRD * nb + i];
+        double h = b[BHS * nb + i];
+        if (!(h > 0.0)) h = tau;
+        double t = 0.0;
+        int acc = 0, att = 0;
+        while (t < tau) {
+            if (att >= A.max_substeps) {
+                raise_error(sc, E_SUBSTEP, i, -1);
+                break;
+            }
+            ++att;
+            double hs = h < tau - t ? h : tau - t;
+            double r5, v5, r4, v4;
+            dp54(ph, r0, pg0, pinf, irho, ic, y0, y1, hs, r5, v5, r4, v4);
+            double err = dmax(fabs(r5 - r4) / fabs(r5), fabs(v5 - v4) / dmax(fabs(v5), vfloor));
+            if (!(err == err)) err = INFINITY;
+            if (err <= A.rtol && r5 > 0.0) {
+                t += hs;
+                y0 = r5;
+                y1 = v5;
+                ++acc;
+            }
+            double fac = err > 0.0 ? 0.9 * pow(A.rtol / err, 0.2) : 4.0;
+            if (!(r5 > 0.0)) fac = 0.25;
+            fac = dmin(4.0, dmax(0.25, fac));
+            h = hs * fac;
+        }
+        b[BRR * nb + i] = y0;
+        b[BRD * nb + i] = y1;
+        b[BHS * nb + i] = h;
+        if (A.nsub) A.nsub[i] += acc;
+    }
+}
+
+// one wavefront per bubble: alpha += V delta, dalpha += 4 pi R^2 Rdot delta
+__global__ void __launch_bounds__(256) k_el_scatter(const double *__restrict__ b, long long nb, ElGrid g,
+                                                    double *__restrict__ aD)
+{
+    const int lane = threadIdx.x & 63;
+    const long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (i >= nb) return;
+    const long long N = g.N;
+    int host[3], m;
+    double h;
+    el_support(b, nb, i, g, host, h, m);
+    const double xb[3] = {b[BX_ * nb + i], b[BY_ * nb + i], b[BZ_ * nb + i]};
+    const double R = b[BRR * nb + i], V = b[BRD * nb + i];
+    const double vol = FOUR_PI_3 * R * R * R, rate = 3.0 * FOUR_PI_3 * R * R * V;
+    const int w = 2 * m + 1, tot = w * w * w;
+    for (int o = lane; o < tot; o += 64) {
+        int off[3] = {o % w - m, (o / w) % w - m, o / (w * w) - m};
+        int cc[3];
+        bool out_ = false;
+        double d2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            double xc = (host[d] + off[d] + 0.5) * g.dx;
+            d2 += (xc - xb[d]) * (xc - xb[d]);
+            cc[d] = el_wrap(host[d] + off[d], g.n[d], g.bc[d]);
+            if (cc[d] < 0) out_ = true;
+        }
+        if (out_) continue;
+        double wk = el_kernel(d2, h);
+        if (wk == 0.0) continue;
+        long long c = cc[0] + (long long)g.n[0] * (cc[1] + (long long)g.n[1] * cc[2]);
+        atomicAdd(&aD[c], vol * wk);
+        atomicAdd(&aD[N + c], rate * wk);
+    }
+}
+
+__global__ void k_fill(double *p, long long n, double v)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+struct ElStageArgs {
+    const double *qk, *qn;
+    double *qo;
+    const double *P;      // liquid primitives of qk
+    const double *aD;     // frozen alpha, dalpha
+    const double *dtp;
+    double a, b;
+    int rhs_mode;
+};
+
+// Liquid face between cell (c - e_d) and c: HLLC flux and face-state pressures / normal velocities.
+template <int d>
+__device__ inline void el_face(const double *__restrict__ P, const ElGrid &g, const Phys &ph, const int co[3],
+                               double F[5], double &pL, double &pR, double &uL, double &uR)
+{
+    const long long N = g.N;
+    double st[6][5];
+    for (int o = 0; o < 6; ++o) {
+        int cc[3] = {co[0], co[1], co[2]};
+        bool flip = false;
+        cc[d] = map_coord(co[d] - 3 + o, g.n[d], g.bc[d], flip);
+        long long c = cc[0] + (long long)g.n[0] * (cc[1] + (long long)g.n[1] * cc[2]);
+        for (int v = 0; v < 5; ++v) st[o][v] = P[v * N + c];
+        if (flip) st[o][1 + d] = -st[o][1 + d];
+    }
+    double WL[5], WR[5];
+    for (int v = 0; v < 5; ++v) {
+        WL[v] = weno5(st[0][v], st[1][v], st[2][v], st[3][v], st[4][v]);
+        WR[v] = weno5(st[5][v], st[4][v], st[3][v], st[2][v], st[1][v]);
+    }
+    if (!(WL[0] > 0.0 && WR[0] > 0.0 && WL[4] + ph.pi_inf > 0.0 && WR[4] + ph.pi_inf > 0.0)) {
+        for (int v = 0; v < 5; ++v) {
+            WL[v] = st[2][v];
+            WR[v] = st[3][v];
+        }
+    }
+    double EK[2], cK[2];
+    const double *Ws[2] = {WL, WR};
+    for (int s = 0; s < 2; ++s) {
+        const double *W = Ws[s];
+        EK[s] = (W[4] + ph.gpi) * ph.inv_gm1 + 0.5 * W[0] * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
+        cK[s] = sqrt(ph.gamma * (W[4] + ph.pi_inf) / W[0]);
+    }
+    double ul = WL[1 + d], ur = WR[1 + d];
+    double SL = dmin(ul - cK[0], ur - cK[1]), SR = dmax(ul + cK[0], ur + cK[1]);
+    double mL = WL[0] * (SL - ul), mR = WR[0] * (SR - ur);
+    double Ss = (WR[4] - WL[4] + ul * mL - ur * mR) / (mL - mR);
+    int side, star;
+    if (SL >= 0.0) { side = 0; star = 0; }
+    else if (Ss >= 0.0) { side = 0; star = 1; }
+    else if (SR > 0.0) { side = 1; star = 1; }
+    else { side = 1; star = 0; }
+    const double *W = side ? WR : WL;
+    double SK = side ? SR : SL, un = W[1 + d], ek = EK[side], pk = W[4], rk = W[0];
+    double fac = star ? SK * (Ss - un) / (SK - Ss) : 0.0;
+    F[0] = rk * un + fac * rk;
+    for (int e = 0; e < 3; ++e) F[1 + e] = rk * un * W[1 + e] + (e == d ? pk : 0.0) + fac * rk * (e == d ? SK : W[1 + e]);
+    F[4] = (ek + pk) * un + fac * (ek + pk + rk * Ss * (SK - un));
+    pL = WL[4];
+    pR = WR[4];
+    uL = WL[1 + d];
+    uR = WR[1 + d];
+}
+
+__global__ void __launch_bounds__(256) k_el_stage(ElStageArgs A, ElGrid g, Phys ph)
+{
+    const long long N = g.N;
+    const double dt = A.rhs_mode ? 0.0 : *A.dtp;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
+        int co[3] = {(int)(c % g.n[0]), (int)((c / g.n[0]) % g.n[1]), (int)(c / ((long long)g.n[0] * g.n[1]))};
+        double L[5] = {0, 0, 0, 0, 0}, gradp[3], divpu = 0.0;
+        auto dir = [&](auto dtag) {
+            constexpr int d = decltype(dtag)::value;
+            int hi[3] = {co[0], co[1], co[2]};
+            hi[d] += 1;
+            double Fl[5], Fh[5], pl0, pr0, ul0, ur0, pl1, pr1, ul1, ur1;
+            el_face<d>(A.P, g, ph, co, Fl, pl0, pr0, ul0, ur0);
+            el_face<d>(A.P, g, ph, hi, Fh, pl1, pr1, ul1, ur1);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) L[k] += (Fl[k] - Fh[k]) * g.inv_dx;
+            gradp[d] = (0.5 * (pl1 + pr1) - 0.5 * (pl0 + pr0)) * g.inv_dx;
+            divpu += (0.5 * (pl1 * ul1 + pr1 * ur1) - 0.5 * (pl0 * ul0 + pr0 * ur0)) * g.inv_dx;
+        };
+        dir(std::integral_constant<int, 0>{});
+        dir(std::integral_constant<int, 1>{});
+        dir(std::integral_constant<int, 2>{});
+        double rho = A.P[c], E = A.qk[4 * N + c];
+        double a = A.aD[c], D = A.aD[N + c];
+        double ioma = 1.0 / (1.0 - a);
+        L[0] += rho * D * ioma;
+        for (int d = 0; d < 3; ++d) L[1 + d] += rho * A.P[(1 + d) * N + c] * D * ioma - a * gradp[d] * ioma;
+        L[4] += E * D * ioma - a * divpu * ioma;
+        for (int k = 0; k < 5; ++k) {
+            long long o = (long long)k * N + c;
+            if (A.rhs_mode) A.qo[o] = L[k];
+            else {
+                double r = A.b * (A.qk[o] + dt * L[k]);
+                if (A.a != 0.0) r += A.a * A.qn[o];
+                A.qo[o] = r;
+            }
+        }
+    }
+}
+
+}  // namespace bub
