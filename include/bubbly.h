@@ -91,8 +91,20 @@ typedef struct bub_ctx bub_ctx;
 int bub_ctx_create(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas,
                    const bub_bins *bins, const bub_opts *opts, bub_ctx **out);
 
-/* Free a context and its device buffers.  Waits for the device first. */
+/* Free a context.  A context from bub_ctx_create waits for the device and
+ * frees its buffers; one from bub_ctx_create_on only frees host memory (the
+ * caller keeps the device buffer alive until work that uses it has finished). */
 int bub_ctx_destroy(bub_ctx *ctx);
+
+/* Device bytes a context needs (bin table, primitive scratch, scalars). */
+int bub_ctx_buffer_bytes(const bub_grid *grid, const bub_bins *bins, size_t *bytes);
+
+/* As bub_ctx_create, but the context lives in `buffer` (caller-owned device
+ * memory of at least bub_ctx_buffer_bytes, 256-byte aligned) and is initialised
+ * by a kernel enqueued on `stream`: no device allocation and no host
+ * synchronisation, so problems can be admitted while others run. */
+int bub_ctx_create_on(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, const bub_bins *bins,
+                      const bub_opts *opts, void *buffer, size_t bytes, void *stream, bub_ctx **out);
 
 /* Sizes: nvar conserved variables, nprim primitive scratch fields, ncells = N,
  * state_bytes = nvar*N*8, work_bytes = the `work` buffer bub_rk3_step needs.
@@ -196,10 +208,60 @@ int bub_lagrangian_rhs(bub_ctx *ctx, const double *ql, const double *alpha_D, do
 int bub_lagrangian_step(bub_ctx *ctx, double *ql, double *bubbles, int64_t nbub, double *alpha_D, double *work,
                         double dt, double *dt_dev, int32_t *nsub, void *stream);
 
+/* ---- Batches: many resident problems advanced together ----
+ * A batch holds up to max_cases problems (contexts of any dimensionality, bin
+ * count, size and bubble mode, all of the batch's precision) with their state q
+ * and work buffer (caller-owned device memory, as for bub_rk3_step).
+ * bub_batch_step advances every member by nsteps CFL-limited SSP-RK3 steps
+ * (each member its own step size).  The members are dealt, largest first, over
+ * a few internal streams (default priority) so that the kernels of small
+ * problems overlap on the device; the internal streams start after the work
+ * already queued on `stream`, and `stream` continues only after all of them,
+ * so to the caller the call is one stream-ordered operation.  Each member runs
+ * exactly the kernels of bub_rk3_step on its own buffers: its result is
+ * bitwise the same as bub_rk3_step alone, whatever the other members are.
+ * Members keep their own error word (bub_last_error or bub_error_copy on the
+ * member's context).  A context may be in one batch slot at a time and must
+ * not be destroyed, nor its buffers freed, while it is a member or while a
+ * step that included it may still be running.  Not thread-safe. */
+typedef struct bub_batch bub_batch;
+
+/* BUB_EHIP if the internal streams or events cannot be created. */
+int bub_batch_create(int precision, int max_cases, bub_batch **out);
+/* Waits for the internal streams, then releases them. */
+int bub_batch_destroy(bub_batch *batch);
+
+/* Add a member; *slot receives its handle.  BUB_EINVAL if the batch is full,
+ * the precision differs, the context is already a member, or q and work
+ * overlap.  A member whose (ndim, nb) class was autotuned gets that class's
+ * stage tile shape. */
+int bub_batch_add(bub_batch *batch, bub_ctx *ctx, double *q, double *work, int *slot);
+int bub_batch_remove(bub_batch *batch, int slot);
+
+/* nsteps steps of every member, ordered on `stream` (no host synchronisation). */
+int bub_batch_step(bub_batch *batch, int nsteps, void *stream);
+
+/* Members, total cells and total cell-bins of the current members. */
+int bub_batch_info(const bub_batch *batch, int *ncases, int64_t *cells, int64_t *cell_bins);
+
+/* Autotuner of the stage kernel's tile shape per (ndim, nb) class: for every
+ * member whose class has no tuned shape yet, bub_autotune on that member (its
+ * work buffer receives right-hand sides; its state is not changed) picks the
+ * fastest shape, which then applies to every member of the class, present and
+ * later.  *classes (may be NULL) receives the number of tuned classes.
+ * Synchronises `stream`; results do not depend on the tile shape. */
+int bub_batch_autotune(bub_batch *batch, int reps, int *classes, void *stream);
+
 /* Synchronises `stream`, then reports and clears the sticky device error word:
  * *code (BUB_OK or a device BUB_E* code), *cell (first failing cell or -1),
  * *bin (failing bin or -1).  Any output pointer may be NULL. */
 int bub_last_error(bub_ctx *ctx, int *code, int64_t *cell, int *bin, void *stream);
+
+/* Non-blocking form of bub_last_error for callers that must not synchronise:
+ * enqueues on `stream` a copy of the error word into dst (device-accessible
+ * int64 [3]: code, first failing cell or -1, failing bin or -1) and returns.
+ * The word is not cleared. */
+int bub_error_copy(const bub_ctx *ctx, int64_t *dst, void *stream);
 
 /* Human-readable name of a BUB_* code (static string). */
 const char *bub_strerror(int code);

@@ -55,6 +55,10 @@ _SIGS = {
     "bub_ctx_create": [ctypes.POINTER(_Grid), ctypes.POINTER(_Liquid), ctypes.POINTER(_Gas),
                        ctypes.POINTER(_Bins), ctypes.POINTER(_Opts), ctypes.POINTER(_vp)],
     "bub_ctx_destroy": [_vp],
+    "bub_ctx_buffer_bytes": [ctypes.POINTER(_Grid), ctypes.POINTER(_Bins), ctypes.POINTER(ctypes.c_size_t)],
+    "bub_ctx_create_on": [ctypes.POINTER(_Grid), ctypes.POINTER(_Liquid), ctypes.POINTER(_Gas),
+                          ctypes.POINTER(_Bins), ctypes.POINTER(_Opts), _vp, ctypes.c_size_t, _vp,
+                          ctypes.POINTER(_vp)],
     "bub_layout": [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64),
                    ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
     "bub_bins_get": [_vp, _dp, _dp],
@@ -64,6 +68,7 @@ _SIGS = {
     "bub_moments": [_vp, _vp, _vp, _vp],
     "bub_last_error": [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_int),
                        _vp],
+    "bub_error_copy": [_vp, _vp, _vp],
     "bub_bubble_advance": [_vp, _vp, ctypes.c_double, _vp, _vp],
     "bub_lagrangian_layout": [_vp, _i64, ctypes.POINTER(ctypes.c_size_t)],
     "bub_lagrangian_bubbles": [_vp, _vp, _vp, _i64, _vp],
@@ -77,6 +82,13 @@ _SIGS = {
     "bub_tile_set": [_vp, ctypes.c_int],
     "bub_tile_get": [_vp, ctypes.POINTER(ctypes.c_int)],
     "bub_autotune": [_vp, _vp, _vp, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int), _vp],
+    "bub_batch_create": [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)],
+    "bub_batch_destroy": [_vp],
+    "bub_batch_add": [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_int)],
+    "bub_batch_remove": [_vp, ctypes.c_int],
+    "bub_batch_step": [_vp, ctypes.c_int, _vp],
+    "bub_batch_info": [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
+    "bub_batch_autotune": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _vp],
     "bub_profile": [_vp, ctypes.c_int],
     "bub_profile_read": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)],
 }
@@ -128,7 +140,10 @@ class Context:
     """One problem (grid, physics, bins, options) on the current device."""
 
     def __init__(self, ndim, n, dx, bc, nb, r0_median=10e-6, sigma_ln=0.3, liquid=None, gas=None, cfl=0.3,
-                 precision=PREC_FP64, bubble_mode=BUBBLES_UNSPLIT, sub_rtol=1e-4, max_substeps=10000):
+                 precision=PREC_FP64, bubble_mode=BUBBLES_UNSPLIT, sub_rtol=1e-4, max_substeps=10000,
+                 torch_buffer=False, stream=None):
+        """torch_buffer=True: the context's device memory is a torch tensor and it is initialised on
+        `stream` (bub_ctx_create_on): no allocation call and no host synchronisation."""
         L = lib()
         liquid = liquid or dict(gamma=7.1, pi_inf=3.06e8, rho0=1000.0, p0=101325.0)
         gas = gas or dict(kappa=1.4, sigma=0.0728, mu=1e-3, pv=0.0)
@@ -144,8 +159,19 @@ class Context:
         bn = _Bins(nb, r0_median, sigma_ln)
         op = _Opts(cfl, precision, bubble_mode, sub_rtol, max_substeps)
         h = _vp()
-        _check(L.bub_ctx_create(ctypes.byref(g), ctypes.byref(lq), ctypes.byref(gs), ctypes.byref(bn),
-                                ctypes.byref(op), ctypes.byref(h)), "bub_ctx_create")
+        self._buf = None
+        if torch_buffer:
+            nbytes = ctypes.c_size_t()
+            _check(L.bub_ctx_buffer_bytes(ctypes.byref(g), ctypes.byref(bn), ctypes.byref(nbytes)),
+                   "bub_ctx_buffer_bytes")
+            self._buf = torch.empty((nbytes.value + 256,), dtype=torch.uint8, device="cuda")
+            addr = (self._buf.data_ptr() + 255) & ~255
+            _check(L.bub_ctx_create_on(ctypes.byref(g), ctypes.byref(lq), ctypes.byref(gs), ctypes.byref(bn),
+                                       ctypes.byref(op), _vp(addr), nbytes.value, _stream(stream), ctypes.byref(h)),
+                   "bub_ctx_create_on")
+        else:
+            _check(L.bub_ctx_create(ctypes.byref(g), ctypes.byref(lq), ctypes.byref(gs), ctypes.byref(bn),
+                                    ctypes.byref(op), ctypes.byref(h)), "bub_ctx_create")
         self._h = h
         self.ndim = ndim
         self.n = tuple(g.n)
@@ -164,6 +190,7 @@ class Context:
         if getattr(self, "_h", None):
             lib().bub_ctx_destroy(self._h)
             self._h = None
+        self._buf = None
 
     def __del__(self):
         try:
@@ -311,6 +338,77 @@ class Context:
         _check(lib().bub_last_error(self._h, ctypes.byref(code), ctypes.byref(cell), ctypes.byref(b),
                                     _stream(stream)), "bub_last_error")
         return code.value, cell.value, b.value
+
+    def error_copy(self, dst: torch.Tensor, stream=None):
+        """Enqueue a copy of the error word (code, cell, bin) into the int64 device tensor dst[3]."""
+        if not dst.is_cuda or dst.dtype != torch.int64 or dst.numel() < 3 or not dst.is_contiguous():
+            raise ValueError("dst must be a contiguous int64 GPU tensor of at least 3 elements")
+        _check(lib().bub_error_copy(self._h, _vp(dst.data_ptr()), _stream(stream)), "bub_error_copy")
+
+
+def ctx_buffer_bytes(ndim, n, nb) -> int:
+    """Device bytes of a context's own buffers (bin table, scalars, primitive scratch)."""
+    g = _Grid()
+    g.ndim = ndim
+    for d in range(3):
+        g.n[d] = int(n[d]) if d < len(n) else 1
+        g.dx[d] = 1.0
+    bn = _Bins(nb, 1e-5, 0.3)
+    nbytes = ctypes.c_size_t()
+    _check(lib().bub_ctx_buffer_bytes(ctypes.byref(g), ctypes.byref(bn), ctypes.byref(nbytes)),
+           "bub_ctx_buffer_bytes")
+    return nbytes.value
+
+
+class Batch:
+    """Resident problems advanced together (bub_batch_*): one call steps every member, the members'
+    kernels overlapping on the device over the batch's internal streams."""
+
+    def __init__(self, precision=PREC_FP64, max_cases=64):
+        h = _vp()
+        _check(lib().bub_batch_create(int(precision), int(max_cases), ctypes.byref(h)), "bub_batch_create")
+        self._h = h
+        self.precision = precision
+        self._members = {}     # slot -> (ctx, q, work): keeps buffers alive while resident
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bub_batch_destroy(self._h)
+            self._h = None
+            self._members.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, ctx: Context, q: torch.Tensor, work: torch.Tensor) -> int:
+        if q.numel() * 8 < ctx.state_bytes or work.numel() * 8 < ctx.work_bytes:
+            raise ValueError("state or work buffer too small")
+        slot = ctypes.c_int()
+        _check(lib().bub_batch_add(self._h, ctx._h, _ptr(q), _ptr(work), ctypes.byref(slot)), "bub_batch_add")
+        self._members[slot.value] = (ctx, q, work)
+        return slot.value
+
+    def remove(self, slot: int):
+        _check(lib().bub_batch_remove(self._h, int(slot)), "bub_batch_remove")
+        self._members.pop(slot, None)
+
+    def step(self, nsteps: int = 1, stream=None):
+        _check(lib().bub_batch_step(self._h, int(nsteps), _stream(stream)), "bub_batch_step")
+
+    def info(self):
+        """(members, cells, cell-bins)."""
+        n, c, cb = ctypes.c_int(), _i64(), _i64()
+        _check(lib().bub_batch_info(self._h, ctypes.byref(n), ctypes.byref(c), ctypes.byref(cb)), "bub_batch_info")
+        return n.value, c.value, cb.value
+
+    def autotune(self, reps: int = 3, stream=None) -> int:
+        """Tune the stage tile shape of every new (ndim, nb) class; returns the number of tuned classes."""
+        k = ctypes.c_int()
+        _check(lib().bub_batch_autotune(self._h, int(reps), ctypes.byref(k), _stream(stream)), "bub_batch_autotune")
+        return k.value
 
 
 def context_from_case(case, **kw) -> Context:

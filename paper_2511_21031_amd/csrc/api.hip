@@ -2,6 +2,7 @@
 // checks, and the launch sequences of the ensemble-averaged hot path.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -14,6 +15,8 @@
 #include "split_kernels.hpp"
 #include "stage_kernel.hpp"
 #include "el_kernels.hpp"
+
+#include <vector>
 #include "ctx.hpp"
 
 using namespace bub;
@@ -213,8 +216,58 @@ const char *bub_strerror(int code)
     }
 }
 
-int bub_ctx_create(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, const bub_bins *bins,
-                   const bub_opts *opts, bub_ctx **out)
+}  // extern "C"
+
+namespace {
+
+// Bin table passed by value to the initialising kernel (no host memory to keep alive).
+struct BinTable {
+    double v[3 * NB_MAX];
+};
+
+__global__ void k_ctx_init(double *bins, BinTable t, int n, Scalars *sc)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) bins[i] = t.v[i];
+    if (threadIdx.x == 0) *sc = Scalars{};
+}
+
+__global__ void k_err_copy(const Scalars *sc, int64_t *dst)
+{
+    if (threadIdx.x == 0) {
+        const int code = sc->err_code;
+        dst[0] = code;
+        dst[1] = code ? (int64_t)sc->err_cell : -1;
+        dst[2] = code ? (int64_t)sc->err_bin : -1;
+    }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Device-buffer layout of a context: bin table | scalars | primitive scratch.
+void ctx_buffer_layout(int ndim, long long N, size_t *off_sc, size_t *off_P, size_t *total)
+{
+    *off_sc = align256(sizeof(double) * 3 * NB_MAX);
+    *off_P = *off_sc + align256(sizeof(Scalars));
+    *total = *off_P + align256(sizeof(double) * (size_t)(ndim + 6) * (size_t)N);
+}
+
+void ctx_finish(bub_ctx *c)
+{
+    c->bt.r0 = c->d_bins;
+    c->bt.w = c->d_bins + c->nb;
+    c->bt.pg0 = c->d_bins + 2 * c->nb;
+}
+
+void bin_table(const bub_ctx *c, double *tab)
+{
+    std::memcpy(tab, c->h_r0, sizeof(double) * c->nb);
+    std::memcpy(tab + c->nb, c->h_w, sizeof(double) * c->nb);
+    std::memcpy(tab + 2 * c->nb, c->h_pg0, sizeof(double) * c->nb);
+}
+
+// Validate the inputs and build the host side of a context (no device memory yet).
+int ctx_setup(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, const bub_bins *bins,
+              const bub_opts *opts, bub_ctx **out)
 {
     if (!grid || !liq || !gas || !bins || !opts || !out) return BUB_EINVAL;
     *out = nullptr;
@@ -266,22 +319,6 @@ int bub_ctx_create(const bub_grid *grid, const bub_liquid *liq, const bub_gas *g
         delete c;
         return BUB_EHIP;
     }
-    size_t pbytes = sizeof(double) * (size_t)c->nprim * (size_t)N;
-    if (hipMalloc(&c->d_bins, sizeof(double) * 3 * NB_MAX) != hipSuccess ||
-        hipMalloc(&c->d_P, pbytes) != hipSuccess || hipMalloc(&c->d_sc, sizeof(Scalars)) != hipSuccess) {
-        bub_ctx_destroy(c);
-        return BUB_ENOMEM;
-    }
-    double tab[3 * NB_MAX];
-    std::memcpy(tab, c->h_r0, sizeof(double) * c->nb);
-    std::memcpy(tab + c->nb, c->h_w, sizeof(double) * c->nb);
-    std::memcpy(tab + 2 * c->nb, c->h_pg0, sizeof(double) * c->nb);
-    Scalars zero{};
-    if (hipMemcpy(c->d_bins, tab, sizeof(double) * 3 * c->nb, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->d_sc, &zero, sizeof(Scalars), hipMemcpyHostToDevice) != hipSuccess) {
-        bub_ctx_destroy(c);
-        return BUB_EHIP;
-    }
     c->ph.gamma = liq->gamma;
     c->ph.pi_inf = liq->pi_inf;
     c->ph.gm1 = liq->gamma - 1.0;
@@ -307,13 +344,88 @@ int bub_ctx_create(const bub_grid *grid, const bub_liquid *liq, const bub_gas *g
     return BUB_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int bub_ctx_create(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, const bub_bins *bins,
+                   const bub_opts *opts, bub_ctx **out)
+{
+    bub_ctx *c = nullptr;
+    int rc = ctx_setup(grid, liq, gas, bins, opts, &c);
+    if (rc) return rc;
+    size_t pbytes = sizeof(double) * (size_t)c->nprim * (size_t)c->N;
+    c->owns = true;
+    if (hipMalloc(&c->d_bins, sizeof(double) * 3 * NB_MAX) != hipSuccess ||
+        hipMalloc(&c->d_P, pbytes) != hipSuccess || hipMalloc(&c->d_sc, sizeof(Scalars)) != hipSuccess) {
+        bub_ctx_destroy(c);
+        return BUB_ENOMEM;
+    }
+    double tab[3 * NB_MAX];
+    bin_table(c, tab);
+    Scalars zero{};
+    if (hipMemcpy(c->d_bins, tab, sizeof(double) * 3 * c->nb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_sc, &zero, sizeof(Scalars), hipMemcpyHostToDevice) != hipSuccess) {
+        bub_ctx_destroy(c);
+        return BUB_EHIP;
+    }
+    ctx_finish(c);
+    *out = c;
+    return BUB_OK;
+}
+
+int bub_ctx_buffer_bytes(const bub_grid *grid, const bub_bins *bins, size_t *bytes)
+{
+    if (!grid || !bins || !bytes || grid->ndim < 1 || grid->ndim > 3) return BUB_EINVAL;
+    long long N = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (grid->n[d] < 1) return BUB_EINVAL;
+        N *= grid->n[d];
+    }
+    size_t a, b;
+    ctx_buffer_layout(grid->ndim, N, &a, &b, bytes);
+    return BUB_OK;
+}
+
+int bub_ctx_create_on(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, const bub_bins *bins,
+                      const bub_opts *opts, void *buffer, size_t bytes, void *stream, bub_ctx **out)
+{
+    if (!buffer || ((uintptr_t)buffer & 255)) return BUB_EINVAL;
+    bub_ctx *c = nullptr;
+    int rc = ctx_setup(grid, liq, gas, bins, opts, &c);
+    if (rc) return rc;
+    size_t off_sc, off_P, total;
+    ctx_buffer_layout(c->ndim, c->N, &off_sc, &off_P, &total);
+    if (bytes < total) {
+        delete c;
+        return BUB_EINVAL;
+    }
+    char *base = (char *)buffer;
+    c->owns = false;
+    c->d_bins = (double *)base;
+    c->d_sc = (Scalars *)(base + off_sc);
+    c->d_P = (double *)(base + off_P);
+    BinTable t{};
+    bin_table(c, t.v);
+    hipLaunchKernelGGL(k_ctx_init, dim3(1), dim3(64), 0, (hipStream_t)stream, c->d_bins, t, 3 * c->nb, c->d_sc);
+    if (hipGetLastError() != hipSuccess) {
+        delete c;
+        return BUB_EHIP;
+    }
+    ctx_finish(c);
+    *out = c;
+    return BUB_OK;
+}
+
 int bub_ctx_destroy(bub_ctx *c)
 {
     if (!c) return BUB_EINVAL;
-    (void)hipDeviceSynchronize();
-    if (c->d_bins) (void)hipFree(c->d_bins);
-    if (c->d_P) (void)hipFree(c->d_P);
-    if (c->d_sc) (void)hipFree(c->d_sc);
+    if (c->owns) {
+        (void)hipDeviceSynchronize();
+        if (c->d_bins) (void)hipFree(c->d_bins);
+        if (c->d_P) (void)hipFree(c->d_P);
+        if (c->d_sc) (void)hipFree(c->d_sc);
+    }
     for (ProfRec &r : c->prof) {
         if (r.a) (void)hipEventDestroy(r.a);
         if (r.b) (void)hipEventDestroy(r.b);
@@ -634,6 +746,14 @@ int bub_last_error(bub_ctx *c, int *code, int64_t *cell, int *bin, void *stream)
     return BUB_OK;
 }
 
+int bub_error_copy(const bub_ctx *c, int64_t *dst, void *stream)
+{
+    if (!c || !dst) return BUB_EINVAL;
+    hipLaunchKernelGGL(k_err_copy, dim3(1), dim3(64), 0, (hipStream_t)stream, c->d_sc, dst);
+    HIP_OK(hipGetLastError());
+    return BUB_OK;
+}
+
 int bub_tile_count(const bub_ctx *c, int *count)
 {
     if (!c || !count) return BUB_EINVAL;
@@ -749,6 +869,187 @@ int bub_profile_read(bub_ctx *c, int kind, double *total_ms, int64_t *launches)
     c->prof_used = keep;
     if (total_ms) *total_ms = tot;
     if (launches) *launches = cnt;
+    return BUB_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: resident problems advanced together, fanned out over a few streams
+// ---------------------------------------------------------------------------
+struct bub_batch {
+    struct Member {
+        bub_ctx *ctx = nullptr;
+        double *q = nullptr, *work = nullptr;
+        bool used = false;
+    };
+    int precision = 0;
+    std::vector<Member> slots;
+    static constexpr int NSTREAM = 4;             // one per hardware queue a process gets by default
+    hipStream_t st[NSTREAM] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[NSTREAM] = {};
+    std::vector<std::pair<int, int>> tuned_key;   // (ndim, nb) classes with an autotuned tile
+    std::vector<int> tuned_tile;
+};
+
+namespace {
+
+int batch_class_tile(const bub_batch *b, const bub_ctx *c)
+{
+    for (size_t i = 0; i < b->tuned_key.size(); ++i)
+        if (b->tuned_key[i].first == c->ndim && b->tuned_key[i].second == c->nb) return b->tuned_tile[i];
+    return -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bub_batch_create(int precision, int max_cases, bub_batch **out)
+{
+    if (!out || max_cases < 1 || (precision != BUB_PREC_FP64 && precision != BUB_PREC_MIXED)) return BUB_EINVAL;
+    bub_batch *b = new (std::nothrow) bub_batch();
+    if (!b) return BUB_ENOMEM;
+    b->precision = precision;
+    b->slots.resize(max_cases);
+    bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; k < bub_batch::NSTREAM && ok; ++k)
+        ok = hipStreamCreateWithFlags(&b->st[k], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        bub_batch_destroy(b);
+        return BUB_EHIP;
+    }
+    *out = b;
+    return BUB_OK;
+}
+
+int bub_batch_destroy(bub_batch *b)
+{
+    if (!b) return BUB_EINVAL;
+    for (int k = 0; k < bub_batch::NSTREAM; ++k) {
+        if (b->st[k]) {
+            (void)hipStreamSynchronize(b->st[k]);
+            (void)hipStreamDestroy(b->st[k]);
+        }
+        if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    delete b;
+    return BUB_OK;
+}
+
+int bub_batch_add(bub_batch *b, bub_ctx *c, double *q, double *work, int *slot)
+{
+    if (!b || !c || !q || !work || !slot) return BUB_EINVAL;
+    if (c->opts.precision != b->precision) return BUB_EINVAL;
+    const size_t M = (size_t)c->nvar * (size_t)c->N;
+    if ((q >= work && q < work + 2 * M) || (work >= q && work < q + M)) return BUB_EINVAL;
+    for (size_t i = 0; i < b->slots.size(); ++i) {
+        auto &m = b->slots[i];
+        if (m.used && m.ctx == c) return BUB_EINVAL;
+    }
+    for (size_t i = 0; i < b->slots.size(); ++i) {
+        auto &m = b->slots[i];
+        if (!m.used) {
+            m.ctx = c;
+            m.q = q;
+            m.work = work;
+            m.used = true;
+            const int t = batch_class_tile(b, c);
+            if (t >= 0) c->tile = t;
+            *slot = (int)i;
+            return BUB_OK;
+        }
+    }
+    return BUB_EINVAL;
+}
+
+int bub_batch_remove(bub_batch *b, int slot)
+{
+    if (!b || slot < 0 || slot >= (int)b->slots.size() || !b->slots[slot].used) return BUB_EINVAL;
+    b->slots[slot] = bub_batch::Member{};
+    return BUB_OK;
+}
+
+int bub_batch_info(const bub_batch *b, int *ncases, int64_t *cells, int64_t *cell_bins)
+{
+    if (!b) return BUB_EINVAL;
+    int n = 0;
+    long long cl = 0, cb = 0;
+    for (auto &m : b->slots) {
+        if (!m.used) continue;
+        ++n;
+        cl += m.ctx->N;
+        cb += m.ctx->N * (long long)m.ctx->nb;
+    }
+    if (ncases) *ncases = n;
+    if (cells) *cells = cl;
+    if (cell_bins) *cell_bins = cb;
+    return BUB_OK;
+}
+
+int bub_batch_step(bub_batch *b, int nsteps, void *stream)
+{
+    if (!b || nsteps < 0) return BUB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    // members, largest first, dealt to the least-loaded stream (work ~ cells x variables)
+    std::vector<int> order;
+    for (size_t i = 0; i < b->slots.size(); ++i)
+        if (b->slots[i].used) order.push_back((int)i);
+    if (order.empty() || nsteps == 0) return BUB_OK;
+    auto work_of = [&](int i) { return (double)b->slots[i].ctx->N * (double)b->slots[i].ctx->nvar; };
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return work_of(x) > work_of(y); });
+    double load[bub_batch::NSTREAM] = {};
+    std::vector<int> lane(b->slots.size(), 0);
+    for (int i : order) {
+        int k = 0;
+        for (int j = 1; j < bub_batch::NSTREAM; ++j)
+            if (load[j] < load[k]) k = j;
+        lane[i] = k;
+        load[k] += work_of(i);
+    }
+    const int used = (int)std::min<size_t>(order.size(), bub_batch::NSTREAM);
+    // fork: every lane starts after the work already queued on the caller's stream
+    HIP_OK(hipEventRecord(b->fork, s));
+    for (int k = 0; k < used; ++k) HIP_OK(hipStreamWaitEvent(b->st[k], b->fork, 0));
+    // steps outer, members inner, so every lane's queue is fed from the start
+    for (int step = 0; step < nsteps; ++step)
+        for (int i : order) {
+            auto &m = b->slots[i];
+            int rc = bub_rk3_step(m.ctx, m.q, m.work, 0.0, nullptr, b->st[lane[i]]);
+            if (rc) return rc;
+        }
+    // join: the caller's stream continues after every lane
+    for (int k = 0; k < used; ++k) {
+        HIP_OK(hipEventRecord(b->join[k], b->st[k]));
+        HIP_OK(hipStreamWaitEvent(s, b->join[k], 0));
+    }
+    return BUB_OK;
+}
+
+int bub_batch_autotune(bub_batch *b, int reps, int *classes, void *stream)
+{
+    if (!b || reps < 1) return BUB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int tuned = 0;
+    for (size_t i = 0; i < b->slots.size(); ++i) {
+        auto &m = b->slots[i];
+        if (!m.used) continue;
+        int t = batch_class_tile(b, m.ctx);
+        if (t < 0) {
+            // time the stage kernel's tile shapes on this member (right-hand side into its work buffer)
+            int rc = bub_autotune(m.ctx, m.q, m.work, reps, nullptr, &t, s);
+            if (rc) return rc;
+            b->tuned_key.emplace_back(m.ctx->ndim, m.ctx->nb);
+            b->tuned_tile.push_back(t);
+            ++tuned;
+        }
+        m.ctx->tile = t;
+    }
+    if (classes) *classes = (int)b->tuned_key.size();
+    (void)tuned;
     return BUB_OK;
 }
 

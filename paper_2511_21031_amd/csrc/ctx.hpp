@@ -29,6 +29,7 @@ struct bub_ctx {
     bub::Phys ph{};
     bub::Grid g{};
     bub::Bins bt{};
+    bool owns = true;            // device buffers allocated (and freed) by the library
     int tile = 0;                // stage-kernel tile shape (index into the per-dimension list)
     int prof_on = 0;
     size_t prof_used = 0;

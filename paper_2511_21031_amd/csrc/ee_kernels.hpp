@@ -27,16 +27,16 @@ struct PL {
 
 enum PrimMode { PRIM_ONLY = 0, PRIM_CFL = 1, PRIM_MOMENTS = 2 };
 
+// One cell of the primitive pass; returns max_d (|u_d| + c)/dx_d in CFL mode (0 otherwise).
 template <int D, int MODE>
-__global__ void __launch_bounds__(256) k_prim(const double *__restrict__ q, double *__restrict__ out,
-                                              Grid g, Phys ph, Bins bins, Scalars *sc)
+__device__ __forceinline__ double prim_cell(const double *__restrict__ q, double *__restrict__ out, const Grid &g,
+                                            const Phys &ph, const Bins &bins, Scalars *sc, long long c)
 {
     const long long N = g.N;
     const int nb = bins.nb;
     const int iE = D + 1, iA = D + 2, iNR = D + 3, iNV = D + 3 + nb;
     double wmax = 0.0;
-    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N;
-         c += (long long)gridDim.x * blockDim.x) {
+    {
         double rho = q[c];
         double u[3] = {0.0, 0.0, 0.0};
         double ke = 0.0;
@@ -123,12 +123,26 @@ __global__ void __launch_bounds__(256) k_prim(const double *__restrict__ q, doub
             }
         }
     }
-    if (MODE == PRIM_CFL) {
-        // wavefront max, then one atomic per wave on the bit pattern (positive doubles order as integers)
-        for (int off = 32; off > 0; off >>= 1) wmax = dmax(wmax, __shfl_xor(wmax, off, 64));
-        if ((threadIdx.x & 63) == 0 && wmax > 0.0)
-            atomicMax(&sc->wmax, (unsigned long long)__double_as_longlong(wmax));
-    }
+    return wmax;
+}
+
+// Wavefront max of the CFL wave speed, then one atomic per wave on the bit
+// pattern (positive doubles order as unsigned integers).
+__device__ inline void cfl_reduce(double wmax, Scalars *sc)
+{
+    for (int off = 32; off > 0; off >>= 1) wmax = dmax(wmax, __shfl_xor(wmax, off, 64));
+    if ((threadIdx.x & 63) == 0 && wmax > 0.0) atomicMax(&sc->wmax, (unsigned long long)__double_as_longlong(wmax));
+}
+
+template <int D, int MODE>
+__global__ void __launch_bounds__(256) k_prim(const double *__restrict__ q, double *__restrict__ out,
+                                              Grid g, Phys ph, Bins bins, Scalars *sc)
+{
+    double wmax = 0.0;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < g.N;
+         c += (long long)gridDim.x * blockDim.x)
+        wmax = dmax(wmax, prim_cell<D, MODE>(q, out, g, ph, bins, sc, c));
+    if (MODE == PRIM_CFL) cfl_reduce(wmax, sc);
 }
 
 template <int D>

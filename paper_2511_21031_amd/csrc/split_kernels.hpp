@@ -23,7 +23,8 @@ struct BubbleArgs {
 };
 
 template <int D>
-__global__ void __launch_bounds__(256) k_bubble(BubbleArgs A, Grid g, Phys ph, Bins bins, Scalars *sc)
+__device__ __forceinline__ void bubble_cell(const BubbleArgs &A, const Grid &g, const Phys &ph, const Bins &bins,
+                                            Scalars *sc, long long c)
 {
     const long long N = g.N;
     const int nb = bins.nb;
@@ -32,14 +33,13 @@ __global__ void __launch_bounds__(256) k_bubble(BubbleArgs A, Grid g, Phys ph, B
     const double vfloor = 1e-3 * sqrt(ph.p0 / ph.rho0);
     const double rtol = A.rtol;
     double *q = A.q;
-    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N;
-         c += (long long)gridDim.x * blockDim.x) {
+    {
         double rho = q[c];
         double a = q[iA * N + c];
         if (!(a > 0.0)) {
             if (A.nsub)
                 for (int i = 0; i < nb; ++i) A.nsub[i * N + c] = 0;
-            continue;
+            return;
         }
         double ke = 0.0;
 #pragma unroll
@@ -103,6 +103,14 @@ __global__ void __launch_bounds__(256) k_bubble(BubbleArgs A, Grid g, Phys ph, B
         }
         q[iA * N + c] = a * m3_new / m3_old;
     }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_bubble(BubbleArgs A, Grid g, Phys ph, Bins bins, Scalars *sc)
+{
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < g.N;
+         c += (long long)gridDim.x * blockDim.x)
+        bubble_cell<D>(A, g, ph, bins, sc, c);
 }
 
 }  // namespace bub

@@ -116,21 +116,23 @@ struct StageArgs {
     int ntiles;
 };
 
+// LDS needs of one tile: coef[F] and scr[SCR] of TF, flag[F] bytes.
+template <int D, int TX_, int TY_, int TZ_, typename TF>
+struct StageLds {
+    using G = Geo<D, TX_, TY_, TZ_>;
+    static constexpr int SCR = (G::NCF * G::F > 2 * G::L + 2 * G::F) ? G::NCF * G::F : 2 * G::L + 2 * G::F;
+    static constexpr int BYTES = (G::F + SCR) * (int)sizeof(TF) + G::F;
+};
+
+// The work of one tile (every thread of the workgroup calls it).
 template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF>
-__global__ void __launch_bounds__(BLOCK) k_stage(StageArgs A, Grid g, Phys ph, Bins bins)
+__device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, const Phys &ph, const Bins &bins,
+                                           int tile, TF *__restrict__ s_coef, TF *__restrict__ s_scr,
+                                           unsigned char *__restrict__ s_flag)
 {
     using G = Geo<D, TX_, TY_, TZ_>;
     constexpr int T = G::T, F = G::F, C = G::C, NC = G::NC, NCF = G::NCF, L = G::L;
     constexpr int CPT = (C + BLOCK - 1) / BLOCK;  // cross cells staged per thread
-    constexpr int SCR = (NCF * F > 2 * L + 2 * F) ? NCF * F : 2 * L + 2 * F;
-    __shared__ TF s_coef[F];
-    __shared__ TF s_scr[SCR];
-    __shared__ unsigned char s_flag[F];
-
-    // XCD-aware tile order: consecutive tiles land on the same XCD (blocks are dealt round-robin).
-    const int b = blockIdx.x;
-    const int tile = (b & 7) * A.nblk_per_xcd + (b >> 3);
-    if (tile >= A.ntiles) return;
     const int tx = tile % A.ntile[0];
     const int ty = (tile / A.ntile[0]) % A.ntile[1];
     const int tz = tile / (A.ntile[0] * A.ntile[1]);
@@ -440,6 +442,22 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs A, Grid g, Phys ph, B
         // the next bin's staging writes s_R/s_V only after every thread passed the barrier above,
         // and s_fR/s_fV are rewritten only after the next staging barrier.
     }
+    __syncthreads();  // a following tile on this workgroup may reuse the LDS at once
+}
+
+template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF>
+__global__ void __launch_bounds__(BLOCK) k_stage(StageArgs A, Grid g, Phys ph, Bins bins)
+{
+    using G = Geo<D, TX_, TY_, TZ_>;
+    using S = StageLds<D, TX_, TY_, TZ_, TF>;
+    __shared__ TF s_coef[G::F];
+    __shared__ TF s_scr[S::SCR];
+    __shared__ unsigned char s_flag[G::F];
+    // XCD-aware tile order: consecutive tiles land on the same XCD (blocks are dealt round-robin).
+    const int b = blockIdx.x;
+    const int tile = (b & 7) * A.nblk_per_xcd + (b >> 3);
+    if (tile >= A.ntiles) return;
+    stage_tile<D, TX_, TY_, TZ_, BLOCK, TF>(A, g, ph, bins, tile, s_coef, s_scr, s_flag);
 }
 
 }  // namespace bub

@@ -1,0 +1,214 @@
+"""Batches of resident problems and the continuous-batching server on the GPU.
+
+A batch member runs exactly the kernels of bub_rk3_step on its own buffers
+(only the stream it is queued on and the tile shape the class autotuner picks
+may differ, and results do not depend on either), so its state after k batched
+steps must be bitwise the state after k bub_rk3_step calls on its own context,
+whatever the other members are and whenever the member joined.  The server's
+results must likewise be bitwise the results of each request solved alone, and
+the mixed-precision results must stay within 1e-5 (relative max norm) of the
+FP64 oracle on p and alpha.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.parity import rel_err
+
+pytestmark = pytest.mark.gpu
+TOL_P_ALPHA = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    t = pytest.importorskip("torch")
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def bub(torch):
+    import paper_2511_21031_amd as B
+    B.lib()
+    return B
+
+
+def _gpu(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _members():
+    """Uneven 1D/2D/3D problems, unsplit and split, ragged tiles (name, case, split)."""
+    req = W.c5_stream(count=4, seed=3, scale=0.05)
+    return [
+        ("c1", W.c1(), False),
+        ("2d_periodic", W.random_smooth(2, (70, 37), 1e-4, 5, seed=41), False),
+        ("3d_reflective", W.random_smooth(3, (20, 13, 11), 1e-4, 3, seed=42, bc=1), False),
+        ("3d_collapse_split", W.c3(n=12, nb=5, width=6e-4), True),
+        ("request_split", W.request_case(req[0]), True),
+    ]
+
+
+def _alone(torch, bub, case, split, prec, steps):
+    ctx = bub.context_from_case(case, precision=prec, bubble_mode=bub.BUBBLES_SPLIT if split else bub.BUBBLES_UNSPLIT)
+    q = ctx.init_state(_gpu(torch, case.prim))
+    work = ctx.new_work()
+    for _ in range(steps):
+        ctx.rk3_step(q, work)
+    assert ctx.last_error()[0] == 0
+    return q
+
+
+def _join(torch, bub, batch, case, split, prec):
+    ctx = bub.context_from_case(case, precision=prec, bubble_mode=bub.BUBBLES_SPLIT if split else bub.BUBBLES_UNSPLIT)
+    q = ctx.init_state(_gpu(torch, case.prim))
+    work = ctx.new_work()
+    return batch.add(ctx, q, work), (ctx, q, work)
+
+
+PERSISTENT_SKIP = ("written for the first batch design, a persistent stage kernel pulling (member, tile) items "
+                   "from a device table; its first device run ended in a memory fault whose cause was not found "
+                   "(a host-side emulation of the same sequence under AddressSanitizer is clean), so that kernel "
+                   "was removed; the stream batch below replaces it")
+
+
+@pytest.mark.skip(reason=PERSISTENT_SKIP)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_members_bitwise_equal_alone(torch, bub, prec):
+    P = bub.PREC_FP64 if prec == "fp64" else bub.PREC_MIXED
+    mem = _members()
+    batch = bub.Batch(P, max_cases=8)
+    slots, held, steps = {}, {}, {}
+    for name, case, split in mem[:4]:
+        slots[name], held[name] = _join(torch, bub, batch, case, split, P)
+        steps[name] = 0
+    batch.step(3)
+    for name in slots:
+        steps[name] += 3
+    batch.remove(slots.pop("2d_periodic"))
+    name, case, split = mem[4]
+    slots[name], held[name] = _join(torch, bub, batch, case, split, P)
+    steps[name] = 0
+    batch.step(2)
+    for name in slots:
+        steps[name] += 2
+    torch.cuda.synchronize()
+    for name, case, split in mem:
+        ctx, q, _ = held[name]
+        assert ctx.last_error()[0] == 0, name
+        ref = _alone(torch, bub, case, split, P, steps[name])
+        assert torch.equal(q, ref), (name, (q - ref).abs().max().item())
+    batch.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_stream_batch_members_bitwise_equal_alone(torch, bub, prec):
+    """Members join and leave a running batch; each ends bitwise equal to its problem stepped alone."""
+    P = bub.PREC_FP64 if prec == "fp64" else bub.PREC_MIXED
+    mem = _members()
+    batch = bub.Batch(P, max_cases=8)
+    slots, held, steps = {}, {}, {}
+    for name, case, split in mem[:4]:
+        slots[name], held[name] = _join(torch, bub, batch, case, split, P)
+        steps[name] = 0
+    batch.step(3)
+    for name in slots:
+        steps[name] += 3
+    batch.remove(slots.pop("2d_periodic"))
+    name, case, split = mem[4]
+    slots[name], held[name] = _join(torch, bub, batch, case, split, P)
+    steps[name] = 0
+    n, cells, cb = batch.info()
+    assert n == 4 and cells == sum(held[k][0].ncells for k in slots)
+    batch.step(2)
+    for name in slots:
+        steps[name] += 2
+    torch.cuda.synchronize()
+    for name, case, split in mem:
+        ctx, q, _ = held[name]
+        assert ctx.last_error()[0] == 0, name
+        ref = _alone(torch, bub, case, split, P, steps[name])
+        assert torch.equal(q, ref), (name, (q - ref).abs().max().item())
+    batch.close()
+
+
+def test_stream_batch_class_autotune(torch, bub):
+    """One tuned tile per (ndim, nb) class, applied to members present and joining later; states untouched."""
+    P = bub.PREC_FP64
+    mem = _members()
+    batch = bub.Batch(P, max_cases=8)
+    held = {name: _join(torch, bub, batch, case, split, P)[1] for name, case, split in mem[:4]}
+    before = {k: v[1].clone() for k, v in held.items()}
+    classes = batch.autotune(reps=2)
+    assert classes == len({(c.ndim, c.nb) for _, c, _ in mem[:4]})
+    for k, v in held.items():
+        assert torch.equal(v[1], before[k])
+        assert 0 <= v[0].tile < len(v[0].tiles())
+    # a later member of an already tuned class gets the class's tile
+    name, case, split = mem[0]
+    _, late = _join(torch, bub, batch, case, split, P)
+    assert late[0].tile == held[name][0].tile
+    batch.step(2)
+    torch.cuda.synchronize()
+    for name, case, split in mem[:4]:
+        assert torch.equal(held[name][1], _alone(torch, bub, case, split, P, 2)), name
+    assert torch.equal(late[1], _alone(torch, bub, case, split, P, 2))
+    batch.close()
+
+
+def test_batch_error_word_stays_with_its_member(torch, bub):
+    P = bub.PREC_FP64
+    bad = W.c1(n=64, length=64 * 2.5e-4, nb=3)
+    good = W.c1()
+    batch = bub.Batch(P, max_cases=4)
+    _, (cb, qb, _) = _join(torch, bub, batch, bad, False, P)
+    _, (cg, qg, _) = _join(torch, bub, batch, good, False, P)
+    qb[2, 17] = float("nan")            # energy of cell 17
+    batch.step(2)
+    err = torch.zeros((2, 3), dtype=torch.int64, device="cuda")
+    cb.error_copy(err[0])
+    cg.error_copy(err[1])
+    e = err.cpu().tolist()
+    assert e[0][0] == -4 and e[0][1] == 17
+    assert e[1] == [0, -1, -1]
+    assert torch.equal(qg, _alone(torch, bub, good, False, P, 2))
+    batch.close()
+
+
+def _moment_errors(orc, pb, got, ref):
+    mg, mr = orc.moments(pb, got), orc.moments(pb, ref)
+    return {"p": rel_err(mg[6], mr[6]), "alpha": rel_err(mg[1], mr[1])}
+
+
+def test_server_results_equal_alone_and_match_oracle(torch, bub, orc):
+    from paper_2511_21031_amd.serve import Server, footprint_bytes
+    reqs = W.c5_stream(count=24, seed=7, scale=0.05)
+    cases = {r.rid: W.request_case(r) for r in reqs}
+    fps = [footprint_bytes(c) for c in cases.values()]
+    budget = 3 * max(fps)
+    srv = Server(budget, max_slots=6, precision=bub.PREC_MIXED, bubble_mode=bub.BUBBLES_SPLIT, chunk=4,
+                 keep_results=True)
+    recs = srv.run(reqs, lambda r: cases[r.rid], time_scale=0.0)
+    print(f"peak resident {srv.peak_active} problems, {srv.peak_used} of {budget} B; {len(srv.chunks)} step calls")
+    assert srv.peak_used <= budget and srv.peak_active >= 2 and srv.used == 0
+    assert len(srv.chunks) < sum(r.steps for r in reqs)      # step calls were shared
+    for r, rec in zip(reqs, recs):
+        assert rec.error == 0, (r.rid, rec.error, rec.error_cell, rec.error_bin)
+        ref = _alone(torch, bub, cases[r.rid], True, bub.PREC_MIXED, r.steps).cpu().numpy()
+        assert np.array_equal(rec.result, ref), r.rid
+    # mixed-precision results against the FP64 oracle (each side takes its own CFL steps)
+    checked = 0
+    for r, rec in zip(reqs, recs):
+        case = cases[r.rid]
+        if case.ncells * case.nb > 4000:
+            continue
+        pb = orc.problem_from_case(case, split=1)
+        q = orc.init_state(pb, case.prim)
+        for _ in range(r.steps):
+            orc.rk3_step(pb, q, orc.cfl_dt(pb, q))
+        e = _moment_errors(orc, pb, rec.result, q)
+        assert max(e.values()) < TOL_P_ALPHA, (r.rid, e)
+        checked += 1
+    print("requests checked against the oracle:", checked)
+    assert checked >= 3

@@ -135,3 +135,33 @@ def test_full_size_3d_sampled(torch, bub, orc):
     tot = torch.stack([qg[0].sum(), qg[4].sum()])
     scale = torch.stack([qg[0].abs().sum(), qg[4].abs().sum()])
     assert ((tot - tot0).abs() / scale).max().item() < 1e-12
+
+
+def _serving_requests():
+    """A 1D and a 2D request of the serving stream, at test size (reflective box, Gaussian pulse)."""
+    one = W.c5_stream(count=4, seed=3, scale=0.05)[0]
+    two = [r for r in W.c5_stream(count=24, seed=7, scale=0.05) if r.ndim == 2][0]
+    return {"1d": W.request_case(one), "2d": W.request_case(two)}
+
+
+@pytest.mark.parametrize("kind", ["1d", "2d"])
+def test_split_trajectory_1d_2d_requests(torch, bub, orc, kind):
+    case = _serving_requests()[kind]
+    pb = orc.problem_from_case(case, split=1)
+    q_ref = orc.init_state(pb, case.prim)
+    ctx = bub.context_from_case(case, bubble_mode=bub.BUBBLES_SPLIT)
+    q = ctx.init_state(_gpu(torch, case.prim))
+    work = ctx.new_work()
+    for _ in range(6):
+        dt = orc.cfl_dt(pb, q_ref)
+        orc.rk3_step(pb, q_ref, dt)
+        ctx.rk3_step(q, work, dt)
+    assert ctx.last_error()[0] == 0
+    got = q.cpu().numpy()
+    err = rel_err(got, q_ref)
+    mg, mr = orc.moments(pb, got), orc.moments(pb, q_ref)
+    e_p = rel_err(mg[6], mr[6])
+    e_a = rel_err(mg[1], mr[1])
+    print(f"split {kind} {case.n} nb {case.nb}: max field err", err.max(), "p", e_p, "alpha", e_a)
+    assert err.max() < 10 * RTOL
+    assert e_p < 1e-6 and e_a < 10 * RTOL
