@@ -14,6 +14,15 @@ written by an RK stage: 16 nvar B/cell for stage 1, 24 nvar B/cell for stages
 full RK3 step of the same grid.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--precision fp64|mixed] [--no-cpu-baseline]
+
+Serving workload (--workload serving): the seeded stream of parameter-sweep
+solves (Poisson arrivals; 70% 1D with 200-4000 cells, 25% 2D 64^2-512^2, 5% 3D
+96^3; 11/21/31 bins; void fraction 1e-5..1e-3; 0.1-5 atm pulse; 50-500 steps)
+served by the continuous-batching server in mixed precision, next to the same
+stream solved one request at a time in plain FP64.  Reports solves/s and the
+p50/p99 latency from arrival to result of both.
+
+    python bench.py --workload serving [--requests 512] [--rate 20] [--budget-gib 64] [--no-sequential]
 """
 from __future__ import annotations
 
@@ -68,6 +77,72 @@ def cpu_baseline(case) -> dict:
                       f"{t:.1f} s"}
 
 
+def serving(args):
+    import torch
+    import workloads
+    import paper_2511_21031_amd as bub
+    from paper_2511_21031_amd.serve import Server, run_sequential, summarize
+
+    torch.cuda.set_device(0)
+    reqs = workloads.c5_stream(count=args.requests, rate=args.rate)
+    last = {"t": time.perf_counter()}
+
+    def progress(tag):
+        def f(done, total):
+            now = time.perf_counter()
+            if done == total or now - last["t"] > 10.0:
+                last["t"] = now
+                print(f"[{tag}] {done}/{total} solves done", file=sys.stderr, flush=True)
+        return f
+
+    # warm-up: code objects of every dimensionality and both precisions, on tiny solves
+    warm = workloads.c5_stream(count=12, seed=5, scale=0.05)
+    Server(1 << 34, max_slots=8, chunk=2).run(warm, workloads.request_case, time_scale=0.0)
+    run_sequential(warm[:3], workloads.request_case, bub.PREC_FP64, bub.BUBBLES_SPLIT, time_scale=0.0)
+    torch.cuda.synchronize()
+
+    budget = int(args.budget_gib * (1 << 30))
+    srv = Server(budget, max_slots=64, precision=bub.PREC_MIXED, bubble_mode=bub.BUBBLES_SPLIT, chunk=10)
+    recs = srv.run(reqs, workloads.request_case, progress=progress("served"))
+    t_srv = max(r.finished for r in recs)
+    s_srv = summarize(recs, t_srv)
+    cell_bin_steps = sum(r.n[0] * r.n[1] * r.n[2] * r.nb * r.steps for r in reqs)
+    out = {
+        "metric": "batched solves/s with p50/p99 latency",
+        "value": s_srv["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": len(warm),
+        "ms_per_step": t_srv / len(reqs) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"serving stream of {len(reqs)} ensemble-averaged solves, Poisson arrivals at "
+                               f"{args.rate}/s (70% 1D 200-4000 cells, 25% 2D 64^2-512^2, 5% 3D 96^3; 11/21/31 "
+                               f"bins; 50-500 steps), split bubble sub-stepping, mixed precision",
+                   "hbm_budget_gib": args.budget_gib, "max_slots": 64, "chunk": 10,
+                   "cell_bin_rk_steps": cell_bin_steps},
+        "serving": {"p50_s": s_srv["p50_s"], "p99_s": s_srv["p99_s"], "mean_s": s_srv["mean_s"],
+                    "wall_s": t_srv, "errors": s_srv["errors"], "peak_resident": srv.peak_active,
+                    "peak_bytes": srv.peak_used, "step_calls": len(srv.chunks),
+                    "cell_bin_stage_updates_per_s": 3 * cell_bin_steps / t_srv},
+    }
+    del srv
+    torch.cuda.empty_cache()
+    if not args.no_sequential:
+        seq = run_sequential(reqs, workloads.request_case, bub.PREC_FP64, bub.BUBBLES_SPLIT,
+                             progress=progress("sequential fp64"))
+        t_seq = max(r.finished for r in seq)
+        s_seq = summarize(seq, t_seq)
+        out["sequential_fp64"] = {"solves_per_s": s_seq["solves_per_s"], "p50_s": s_seq["p50_s"],
+                                  "p99_s": s_seq["p99_s"], "wall_s": t_seq, "errors": s_seq["errors"]}
+        out["speedup_vs_sequential_fp64"] = s_srv["solves_per_s"] / s_seq["solves_per_s"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,12 +152,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
+    ap.add_argument("--workload", choices=["stage", "serving"], default="stage")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--rate", type=float, default=20.0, help="serving: mean arrivals per second")
+    ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: HBM budget for resident solves")
+    ap.add_argument("--no-sequential", action="store_true", help="serving: skip the sequential FP64 baseline")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the hot path runs on a single MI355X and this build has no "
               "multi-GPU path (run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serving":
+        serving(args)
+        return
 
     import torch
     import workloads

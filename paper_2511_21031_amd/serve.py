@@ -154,12 +154,14 @@ class Server:
             rec.finished = now
             self.used -= rec.footprint
 
-    def run(self, requests, make_case, time_scale: float = 1.0):
+    def run(self, requests, make_case, time_scale: float = 1.0, progress=None):
         """Serve `requests` (objects with rid, arrival, steps); make_case(request) -> workloads.Case.
 
         Arrival times are seconds from the start of the call, multiplied by time_scale.
+        progress(retired, total), if given, is called after every retirement.
         Returns the Records in request-id order.
         """
+        retired = 0
         pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
         records = {}
         active: dict[int, Record] = {}
@@ -191,6 +193,9 @@ class Server:
             for item in finishing:
                 if item[0].query():
                     self._retire(item, time.perf_counter() - t0)
+                    retired += len(item[1])
+                    if progress is not None:
+                        progress(retired, len(requests))
                 else:
                     still.append(item)
             finishing = still
@@ -229,7 +234,8 @@ def summarize(records, t_total: float) -> dict:
             "errors": int(sum(1 for r in records if r.error))}
 
 
-def run_sequential(requests, make_case, precision, bubble_mode, time_scale: float = 1.0, keep_results=False):
+def run_sequential(requests, make_case, precision, bubble_mode, time_scale: float = 1.0, keep_results=False,
+                   progress=None):
     """Baseline: the same requests one at a time, in arrival order, each on its own context
     with plain bub_rk3_step calls.  A request starts when it has arrived and the previous one
     has finished; its latency is its finish time minus its arrival time."""
@@ -256,4 +262,6 @@ def run_sequential(requests, make_case, precision, bubble_mode, time_scale: floa
             rec.result = q.cpu().numpy()
         ctx.close()
         out.append(rec)
+        if progress is not None:
+            progress(len(out), len(requests))
     return sorted(out, key=lambda x: x.rid)

