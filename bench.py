@@ -37,6 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_WAVE_INSTS = 256 * 2.4e9       # 256 CUs x 2.4 GHz x one wave64 VALU instruction per CU per clock
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_2d1024_nb31_traffic.md")
 
 
@@ -49,16 +50,16 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision: str):
-    """HBM bytes per stage launch from the committed rocprofv3 counter summary, if it matches the sources."""
+def measured_counters(precision: str, kernel: str):
+    """Counter record of the committed rocprofv3 summary for this stage kernel, if it matches the sources."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     want = kernel_hash()
     for line in open(TRAFFIC_FILE):
         if line.startswith("traffic:"):
             rec = json.loads(line.split(":", 1)[1])
-            if rec.get("kernel_hash") == want and rec.get("precision") == precision:
-                return rec["bytes_per_launch"]
+            if rec.get("kernel_hash") == want and rec.get("precision") == precision and rec.get("kernel") == kernel:
+                return rec
     return None
 
 
@@ -103,7 +104,8 @@ def serving(args):
 
     budget = int(args.budget_gib * (1 << 30))
     srv = Server(budget, max_slots=64, precision=bub.PREC_MIXED, bubble_mode=bub.BUBBLES_SPLIT, chunk=10)
-    recs = srv.run(reqs, workloads.request_case, progress=progress("served"))
+    ts = 0.0 if args.burst else 1.0
+    recs = srv.run(reqs, workloads.request_case, time_scale=ts, progress=progress("served"))
     t_srv = max(r.finished for r in recs)
     s_srv = summarize(recs, t_srv)
     cell_bin_steps = sum(r.n[0] * r.n[1] * r.n[2] * r.nb * r.steps for r in reqs)
@@ -120,8 +122,9 @@ def serving(args):
         "vs_baseline": None,
         "dtype": "f64+f32",
         "data": "synthetic",
-        "config": {"workload": f"serving stream of {len(reqs)} ensemble-averaged solves, Poisson arrivals at "
-                               f"{args.rate}/s (70% 1D 200-4000 cells, 25% 2D 64^2-512^2, 5% 3D 96^3; 11/21/31 "
+        "config": {"workload": f"serving stream of {len(reqs)} ensemble-averaged solves, "
+                               + ("all arriving at t=0" if args.burst else f"Poisson arrivals at {args.rate}/s")
+                               + f" (70% 1D 200-4000 cells, 25% 2D 64^2-512^2, 5% 3D 96^3; 11/21/31 "
                                f"bins; 50-500 steps), split bubble sub-stepping, mixed precision",
                    "hbm_budget_gib": args.budget_gib, "max_slots": 64, "chunk": 10,
                    "cell_bin_rk_steps": cell_bin_steps},
@@ -133,7 +136,7 @@ def serving(args):
     del srv
     torch.cuda.empty_cache()
     if not args.no_sequential:
-        seq = run_sequential(reqs, workloads.request_case, bub.PREC_FP64, bub.BUBBLES_SPLIT,
+        seq = run_sequential(reqs, workloads.request_case, bub.PREC_FP64, bub.BUBBLES_SPLIT, time_scale=ts,
                              progress=progress("sequential fp64"))
         t_seq = max(r.finished for r in seq)
         s_seq = summarize(seq, t_seq)
@@ -157,6 +160,7 @@ def main():
     ap.add_argument("--rate", type=float, default=20.0, help="serving: mean arrivals per second")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: HBM budget for resident solves")
     ap.add_argument("--no-sequential", action="store_true", help="serving: skip the sequential FP64 baseline")
+    ap.add_argument("--burst", action="store_true", help="serving: every request arrives at t = 0")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -213,7 +217,10 @@ def main():
     avg_stage_s = stage_ms / 1e3 / max(stage_n, 1)
     bytes_per_launch = (16 + 24 + 24) / 3.0 * nvar * N
     achieved = bytes_per_launch / avg_stage_s / 1e9
-    traffic = measured_traffic(args.precision)
+    tx, ty, tz, blk = ctx.tiles()[best]
+    kname = f"void bub::k_stage<2, {tx}, {ty}, {tz}, {blk}, {'double' if args.precision == 'fp64' else 'float'}>"
+    rec = measured_counters(args.precision, kname)
+    traffic = rec["bytes_per_launch"] if rec else None
     out = {
         "metric": "cell·bin RK-stage updates/s",
         "value": value,
@@ -233,6 +240,11 @@ def main():
                    "tile": list(ctx.tiles()[best]), "autotune_ms": [round(m, 4) for m in tile_ms]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        # the second roofline: VALU issue (one wave64 FP64 instruction per CU per clock at full rate)
+        "valu": ({"wave_insts_per_launch": rec["valu_wave_insts_per_launch"],
+                  "achieved": rec["valu_wave_insts_per_launch"] / avg_stage_s,
+                  "peak": VALU_PEAK_WAVE_INSTS, "unit": "wave-instructions/s",
+                  "frac": rec["valu_wave_insts_per_launch"] / avg_stage_s / VALU_PEAK_WAVE_INSTS} if rec else None),
         "kernels": {"k_stage_avg_ms": stage_ms / max(stage_n, 1), "k_stage_launches": stage_n,
                     "k_prim_avg_ms": prim_ms / max(prim_n, 1), "k_prim_launches": prim_n,
                     "stage_share_of_gpu_time": stage_ms / max(stage_ms + prim_ms, 1e-30)},
