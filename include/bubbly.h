@@ -277,6 +277,15 @@ int bub_tile_info(const bub_ctx *ctx, int idx, int *tx, int *ty, int *tz, int *b
 int bub_tile_set(bub_ctx *ctx, int idx);
 int bub_tile_get(const bub_ctx *ctx, int *idx);
 
+/* Bin groups of the fused stage kernel: `groups` workgroups share each tile,
+ * each taking a contiguous range of bins (the mixture faces are computed by
+ * every group and written by the first).  0 (the default) chooses per launch:
+ * one group when the grid has at least 1024 tiles, else enough groups to give
+ * about 1024 workgroups, with at least two bins per group.  Results do not
+ * depend on the grouping; only the latency of small problems does.  BUB_EINVAL
+ * for groups < 0; values above nb act as nb. */
+int bub_bin_groups(bub_ctx *ctx, int groups);
+
 /* Autotuner: times `reps` launches of the fused stage kernel (right-hand-side
  * form) for every tile shape on the caller's state q (device, read) with
  * `scratch` (device, state_bytes, overwritten) as output, selects the fastest

@@ -81,6 +81,7 @@ _SIGS = {
     "bub_tile_info": [_vp, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4,
     "bub_tile_set": [_vp, ctypes.c_int],
     "bub_tile_get": [_vp, ctypes.POINTER(ctypes.c_int)],
+    "bub_bin_groups": [_vp, ctypes.c_int],
     "bub_autotune": [_vp, _vp, _vp, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int), _vp],
     "bub_batch_create": [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)],
     "bub_batch_destroy": [_vp],
@@ -313,6 +314,10 @@ class Context:
     @tile.setter
     def tile(self, idx: int):
         _check(lib().bub_tile_set(self._h, int(idx)), "bub_tile_set")
+
+    def set_bin_groups(self, groups: int):
+        """Stage-kernel workgroups per tile (0: automatic)."""
+        _check(lib().bub_bin_groups(self._h, int(groups)), "bub_bin_groups")
 
     def autotune(self, q: torch.Tensor, scratch: torch.Tensor | None = None, reps: int = 5, stream=None):
         """Time every tile shape on q, keep the fastest; returns (best index, ms per launch per shape)."""

@@ -107,17 +107,28 @@ void tile_info(int *tx, int *ty, int *tz, int *block)
     *block = Tile<D, V>::BLOCK;
 }
 
+template <int D, int S, int CELLS>
+void launch_prim_s(bub_ctx *c, const double *q, double *out, int mode, hipStream_t s)
+{
+    const dim3 grid((unsigned)((c->g.N + CELLS - 1) / CELLS)), block(S * CELLS);
+    if (mode == PRIM_CFL)
+        hipLaunchKernelGGL((k_prim<D, PRIM_CFL, S, CELLS>), grid, block, 0, s, q, out, c->g, c->ph, c->bt, c->d_sc);
+    else if (mode == PRIM_MOMENTS)
+        hipLaunchKernelGGL((k_prim<D, PRIM_MOMENTS, S, CELLS>), grid, block, 0, s, q, out, c->g, c->ph, c->bt, c->d_sc);
+    else
+        hipLaunchKernelGGL((k_prim<D, PRIM_ONLY, S, CELLS>), grid, block, 0, s, q, out, c->g, c->ph, c->bt, c->d_sc);
+}
+
 template <int D>
 int launch_prim(bub_ctx *c, const double *q, double *out, int mode, hipStream_t s)
 {
-    int nbk = blocks_for(c->g.N);
     long pr = prof_begin(c, BUB_K_PRIM, s);
-    if (mode == PRIM_CFL)
-        hipLaunchKernelGGL((k_prim<D, PRIM_CFL>), dim3(nbk), dim3(256), 0, s, q, out, c->g, c->ph, c->bt, c->d_sc);
-    else if (mode == PRIM_MOMENTS)
-        hipLaunchKernelGGL((k_prim<D, PRIM_MOMENTS>), dim3(nbk), dim3(256), 0, s, q, out, c->g, c->ph, c->bt, c->d_sc);
-    else
-        hipLaunchKernelGGL((k_prim<D, PRIM_ONLY>), dim3(nbk), dim3(256), 0, s, q, out, c->g, c->ph, c->bt, c->d_sc);
+    switch (slots_for(c->g.N)) {
+    case 1: launch_prim_s<D, 1, 256>(c, q, out, mode, s); break;
+    case 2: launch_prim_s<D, 2, 64>(c, q, out, mode, s); break;
+    case 4: launch_prim_s<D, 4, 64>(c, q, out, mode, s); break;
+    default: launch_prim_s<D, 8, 64>(c, q, out, mode, s); break;
+    }
     prof_end(c, pr, s);
     return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
 }
@@ -131,7 +142,21 @@ int launch_stage_t(bub_ctx *c, StageArgs A, hipStream_t s)
     A.ntile[1] = (c->g.n[1] + G::TY - 1) / G::TY;
     A.ntile[2] = (c->g.n[2] + G::TZ - 1) / G::TZ;
     A.ntiles = A.ntile[0] * A.ntile[1] * A.ntile[2];
-    A.nblk_per_xcd = (A.ntiles + 7) / 8;
+    // bin groups: small grids give each tile several workgroups (a range of bins each) so the launch
+    // still fills the chip; large grids keep one workgroup per tile (no repeated mixture faces)
+    int ng = c->bin_groups;
+    if (ng <= 0) {
+        constexpr int target = 1024;   // work items that keep 256 CUs busy
+        ng = A.ntiles >= target ? 1 : (target + A.ntiles - 1) / A.ntiles;
+        const int cap = (c->nb + 1) / 2;  // at least two bins per group
+        if (ng > cap) ng = cap;
+    }
+    if (ng < 1) ng = 1;
+    if (ng > c->nb) ng = c->nb;
+    A.bpg = (c->nb + ng - 1) / ng;
+    A.ngroups = (c->nb + A.bpg - 1) / A.bpg;
+    A.nitems = A.ntiles * A.ngroups;
+    A.nblk_per_xcd = (A.nitems + 7) / 8;
     long pr = prof_begin(c, BUB_K_STAGE, s);
     hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF>), dim3(8 * A.nblk_per_xcd),
                        dim3(TC::BLOCK), 0, s, A, c->g, c->ph, c->bt);
@@ -146,6 +171,24 @@ int launch_stage_v(bub_ctx *c, StageArgs A, hipStream_t s)
     return launch_stage_t<D, V, double>(c, A, s);
 }
 
+template <int D, int S, int CELLS>
+void launch_bubble_s(bub_ctx *c, const BubbleArgs &B, hipStream_t s)
+{
+    const dim3 grid((unsigned)((c->g.N + CELLS - 1) / CELLS)), block(S * CELLS);
+    hipLaunchKernelGGL((k_bubble<D, S, CELLS>), grid, block, 0, s, B, c->g, c->ph, c->bt, c->d_sc);
+}
+
+template <int D>
+void launch_bubble_d(bub_ctx *c, const BubbleArgs &B, hipStream_t s)
+{
+    switch (slots_for(c->g.N)) {
+    case 1: launch_bubble_s<D, 1, 256>(c, B, s); break;
+    case 2: launch_bubble_s<D, 2, 64>(c, B, s); break;
+    case 4: launch_bubble_s<D, 4, 64>(c, B, s); break;
+    default: launch_bubble_s<D, 8, 64>(c, B, s); break;
+    }
+}
+
 int bubble(bub_ctx *c, double *q, const double *taup, double tau_scale, double tau_fixed, int *nsub,
            hipStream_t s)
 {
@@ -157,12 +200,11 @@ int bubble(bub_ctx *c, double *q, const double *taup, double tau_scale, double t
     B.rtol = c->opts.sub_rtol > 0.0 ? c->opts.sub_rtol : 1e-4;
     B.max_substeps = c->opts.max_substeps > 0 ? c->opts.max_substeps : 10000;
     B.nsub = nsub;
-    int nbk = blocks_for(c->g.N);
     long pr = prof_begin(c, BUB_K_OTHER, s);
     switch (c->ndim) {
-    case 1: hipLaunchKernelGGL((k_bubble<1>), dim3(nbk), dim3(256), 0, s, B, c->g, c->ph, c->bt, c->d_sc); break;
-    case 2: hipLaunchKernelGGL((k_bubble<2>), dim3(nbk), dim3(256), 0, s, B, c->g, c->ph, c->bt, c->d_sc); break;
-    default: hipLaunchKernelGGL((k_bubble<3>), dim3(nbk), dim3(256), 0, s, B, c->g, c->ph, c->bt, c->d_sc); break;
+    case 1: launch_bubble_d<1>(c, B, s); break;
+    case 2: launch_bubble_d<2>(c, B, s); break;
+    default: launch_bubble_d<3>(c, B, s); break;
     }
     prof_end(c, pr, s);
     return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
@@ -751,6 +793,13 @@ int bub_error_copy(const bub_ctx *c, int64_t *dst, void *stream)
     if (!c || !dst) return BUB_EINVAL;
     hipLaunchKernelGGL(k_err_copy, dim3(1), dim3(64), 0, (hipStream_t)stream, c->d_sc, dst);
     HIP_OK(hipGetLastError());
+    return BUB_OK;
+}
+
+int bub_bin_groups(bub_ctx *c, int groups)
+{
+    if (!c || groups < 0) return BUB_EINVAL;
+    c->bin_groups = groups;
     return BUB_OK;
 }
 

@@ -31,6 +31,7 @@ struct bub_ctx {
     bub::Bins bt{};
     bool owns = true;            // device buffers allocated (and freed) by the library
     int tile = 0;                // stage-kernel tile shape (index into the per-dimension list)
+    int bin_groups = 0;          // stage-kernel workgroups per tile (0: chosen per launch from the tile count)
     int prof_on = 0;
     size_t prof_used = 0;
     std::vector<ProfRec> prof;

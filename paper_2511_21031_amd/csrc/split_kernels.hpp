@@ -1,11 +1,13 @@
 // Bubble half-step of the Strang splitting (Sec. 3) for gfx950.
 //
-// One thread per cell walks its bins in order (the paper's per-cell bin loop);
-// each (R, Rdot) pair is advanced over tau by Keller--Miksis with the cell's
+// Every (R, Rdot) pair is advanced over tau by Keller--Miksis with its cell's
 // liquid state frozen, using the embedded SSP-RK3 / Heun-RK2 pair that shares
-// the first two stages.  Lanes of a wave hold neighbouring cells, whose bins
-// take similar sub-step counts, so divergence stays low.  Every attempt counts
-// toward max_substeps, so every lane leaves the loop.
+// the first two stages.  A workgroup owns consecutive cells and gives each cell
+// S threads: the lanes of a wave hold neighbouring cells of the same bin subset
+// (bins slot, slot + S, ...), whose sub-step counts are similar, so divergence
+// stays low, and a small problem still spreads over S times more threads than
+// cells.  Every attempt counts toward max_substeps, so every lane leaves its
+// loop.
 #pragma once
 
 #include "device_common.hpp"
@@ -22,25 +24,66 @@ struct BubbleArgs {
     int *nsub;            // [nb][N] accepted sub-steps, or null
 };
 
-template <int D>
-__device__ __forceinline__ void bubble_cell(const BubbleArgs &A, const Grid &g, const Phys &ph, const Bins &bins,
-                                            Scalars *sc, long long c)
+
+// Adaptive integration of one bin over tau: (y0, y1) = (R, Rdot) in, advanced values out.
+// Returns the accepted sub-steps; raises E_SUBSTEP when the attempt budget runs out.
+__device__ inline int bubble_bin(const Phys &ph, double &y0, double &y1, double r0, double pg0, double pl,
+                                 double irhol, double ic, double tau, double rtol, double vfloor, int max_substeps,
+                                 Scalars *sc, long long c, int i)
 {
+    double t = 0.0, h = tau;
+    int accepted = 0, attempts = 0;
+    while (t < tau) {
+        if (attempts >= max_substeps) {
+            raise_error(sc, E_SUBSTEP, c, i);
+            break;
+        }
+        ++attempts;
+        if (h > tau - t) h = tau - t;
+        double k1r = y1, k1v = km_rddot(ph, y0, y1, r0, pg0, pl, irhol, ic);
+        double a0 = y0 + h * k1r, a1 = y1 + h * k1v;
+        double k2r = a1, k2v = km_rddot(ph, a0, a1, r0, pg0, pl, irhol, ic);
+        double b0 = 0.75 * y0 + 0.25 * (a0 + h * k2r), b1 = 0.75 * y1 + 0.25 * (a1 + h * k2v);
+        double e0 = y0 + 0.5 * h * (k1r + k2r), e1 = y1 + 0.5 * h * (k1v + k2v);
+        double k3r = b1, k3v = km_rddot(ph, b0, b1, r0, pg0, pl, irhol, ic);
+        double n0 = y0 * (1.0 / 3.0) + (2.0 / 3.0) * (b0 + h * k3r);
+        double n1 = y1 * (1.0 / 3.0) + (2.0 / 3.0) * (b1 + h * k3v);
+        double err = dmax(fabs(n0 - e0) / fabs(n0), fabs(n1 - e1) / dmax(fabs(n1), vfloor));
+        if (!(err == err)) err = INFINITY;
+        if (err <= rtol && n0 > 0.0) {
+            t += h;
+            y0 = n0;
+            y1 = n1;
+            ++accepted;
+        }
+        double fac = err > 0.0 ? 0.9 * pow(rtol / err, 1.0 / 3.0) : 4.0;
+        if (!(n0 > 0.0)) fac = 0.25;
+        fac = dmin(4.0, dmax(0.25, fac));
+        h *= fac;
+    }
+    return accepted;
+}
+
+// One bubble half-step over the whole grid; grid = ceil(N / CELLS) workgroups of CELLS * S
+// threads (S threads per cell; S = 1 walks all bins of a cell in one thread).  With S > 1 the
+// slots first pool sum w (nR)^3 for n (one barrier), then each advances its bins, posts its part
+// of sum w R^3 before and after, and bumps the cell's LDS counter; the slot that arrives last
+// updates alpha, so waves whose bins need fewer sub-steps leave without waiting.
+template <int D, int S, int CELLS>
+__global__ void __launch_bounds__(S * CELLS) k_bubble(BubbleArgs A, Grid g, Phys ph, Bins bins, Scalars *sc)
+{
+    const int cl = S == 1 ? (int)threadIdx.x : (int)threadIdx.x % CELLS;
+    const int slot = S == 1 ? 0 : (int)threadIdx.x / CELLS;
     const long long N = g.N;
+    const long long c = (long long)blockIdx.x * CELLS + cl;
+    const bool live = c < N;
     const int nb = bins.nb;
     const int iE = D + 1, iA = D + 2, iNR = D + 3, iNV = D + 3 + nb;
-    const double tau = A.taup ? *A.taup * A.tau_scale : A.tau_fixed;
-    const double vfloor = 1e-3 * sqrt(ph.p0 / ph.rho0);
-    const double rtol = A.rtol;
     double *q = A.q;
-    {
+    double a = 0.0, pl = 0.0, irhol = 0.0, ic = 0.0;
+    if (live) {
         double rho = q[c];
-        double a = q[iA * N + c];
-        if (!(a > 0.0)) {
-            if (A.nsub)
-                for (int i = 0; i < nb; ++i) A.nsub[i * N + c] = 0;
-            return;
-        }
+        a = q[iA * N + c];
         double ke = 0.0;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -49,68 +92,73 @@ __device__ __forceinline__ void bubble_cell(const BubbleArgs &A, const Grid &g, 
         }
         ke *= 0.5 / rho;
         double oma = 1.0 - a;
-        double pl = ph.gm1 * (q[iE * N + c] - ke) / oma - ph.gpi;
-        double rhol = rho / oma;
-        double irhol = frcp(rhol);
-        double ic = frcp(sqrt(ph.gamma * (pl + ph.pi_inf) * irhol));
-        double s3 = 0.0;
-        for (int i = 0; i < nb; ++i) {
+        pl = ph.gm1 * (q[iE * N + c] - ke) / oma - ph.gpi;
+        irhol = frcp(rho / oma);
+        ic = frcp(sqrt(ph.gamma * (pl + ph.pi_inf) * irhol));
+    }
+    const bool act = live && a > 0.0;
+    // n from sum w (nR)^3
+    double s3 = 0.0;
+    if (act)
+        for (int i = slot; i < nb; i += S) {
             double x = q[(iNR + i) * N + c];
             s3 += bins.w[i] * (x * x * x);
         }
-        double n = sqrt(FOUR_PI_3 * s3 / a);
-        double in = frcp(n);
-        double m3_old = 0.0, m3_new = 0.0;
-        for (int i = 0; i < nb; ++i) {
-            const double r0 = bins.r0[i], pg0 = bins.pg0[i];
+    [[maybe_unused]] double *s_a = nullptr, *s_b = nullptr;
+    [[maybe_unused]] unsigned *s_cnt = nullptr;
+    if constexpr (S > 1) {
+        __shared__ double s_pa[S][CELLS], s_pb[S][CELLS];
+        __shared__ unsigned s_pc[CELLS];
+        s_a = &s_pa[0][0];
+        s_b = &s_pb[0][0];
+        s_cnt = s_pc;
+        s_a[slot * CELLS + cl] = s3;
+        if (slot == 0) s_cnt[cl] = 0u;
+        __syncthreads();
+        s3 = 0.0;
+#pragma unroll
+        for (int k = 0; k < S; ++k) s3 += s_a[k * CELLS + cl];
+        __syncthreads();   // s_a is reused for the alpha sums
+    }
+    const double tau = A.taup ? *A.taup * A.tau_scale : A.tau_fixed;
+    const double vfloor = 1e-3 * sqrt(ph.p0 / ph.rho0);
+    double m3_old = 0.0, m3_new = 0.0;
+    if (act) {
+        const double n = sqrt(FOUR_PI_3 * s3 / a);
+        const double in = frcp(n);
+        for (int i = slot; i < nb; i += S) {
             double y0 = q[(iNR + i) * N + c] * in;
             double y1 = q[(iNV + i) * N + c] * in;
-            m3_old += bins.w[i] * y0 * y0 * y0;
-            double t = 0.0, h = tau;
-            int accepted = 0, attempts = 0;
-            while (t < tau) {
-                if (attempts >= A.max_substeps) {
-                    raise_error(sc, E_SUBSTEP, c, i);
-                    break;
-                }
-                ++attempts;
-                if (h > tau - t) h = tau - t;
-                double k1r = y1, k1v = km_rddot(ph, y0, y1, r0, pg0, pl, irhol, ic);
-                double a0 = y0 + h * k1r, a1 = y1 + h * k1v;
-                double k2r = a1, k2v = km_rddot(ph, a0, a1, r0, pg0, pl, irhol, ic);
-                double b0 = 0.75 * y0 + 0.25 * (a0 + h * k2r), b1 = 0.75 * y1 + 0.25 * (a1 + h * k2v);
-                double e0 = y0 + 0.5 * h * (k1r + k2r), e1 = y1 + 0.5 * h * (k1v + k2v);
-                double k3r = b1, k3v = km_rddot(ph, b0, b1, r0, pg0, pl, irhol, ic);
-                double n0 = y0 * (1.0 / 3.0) + (2.0 / 3.0) * (b0 + h * k3r);
-                double n1 = y1 * (1.0 / 3.0) + (2.0 / 3.0) * (b1 + h * k3v);
-                double err = dmax(fabs(n0 - e0) / fabs(n0), fabs(n1 - e1) / dmax(fabs(n1), vfloor));
-                if (!(err == err)) err = INFINITY;
-                if (err <= rtol && n0 > 0.0) {
-                    t += h;
-                    y0 = n0;
-                    y1 = n1;
-                    ++accepted;
-                }
-                double fac = err > 0.0 ? 0.9 * pow(rtol / err, 1.0 / 3.0) : 4.0;
-                if (!(n0 > 0.0)) fac = 0.25;
-                fac = dmin(4.0, dmax(0.25, fac));
-                h *= fac;
-            }
+            const double wi = bins.w[i];
+            m3_old += wi * y0 * y0 * y0;
+            int acc = bubble_bin(ph, y0, y1, bins.r0[i], bins.pg0[i], pl, irhol, ic, tau, A.rtol, vfloor,
+                                 A.max_substeps, sc, c, i);
             q[(iNR + i) * N + c] = n * y0;
             q[(iNV + i) * N + c] = n * y1;
-            m3_new += bins.w[i] * y0 * y0 * y0;
-            if (A.nsub) A.nsub[i * N + c] = accepted;
+            m3_new += wi * y0 * y0 * y0;
+            if (A.nsub) A.nsub[i * N + c] = acc;
         }
-        q[iA * N + c] = a * m3_new / m3_old;
+    } else if (live && A.nsub) {
+        for (int i = slot; i < nb; i += S) A.nsub[i * N + c] = 0;
     }
-}
-
-template <int D>
-__global__ void __launch_bounds__(256) k_bubble(BubbleArgs A, Grid g, Phys ph, Bins bins, Scalars *sc)
-{
-    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < g.N;
-         c += (long long)gridDim.x * blockDim.x)
-        bubble_cell<D>(A, g, ph, bins, sc, c);
+    if constexpr (S == 1) {
+        if (act) q[iA * N + c] = a * m3_new / m3_old;   // alpha = (4 pi/3) n mean(R^3) at fixed n
+    } else {
+        s_a[slot * CELLS + cl] = m3_old;
+        s_b[slot * CELLS + cl] = m3_new;
+        __threadfence_block();
+        const unsigned arrived = atomicAdd(&s_cnt[cl], 1u);
+        if (arrived == S - 1 && act) {
+            __threadfence_block();
+            double mo = 0.0, mn = 0.0;
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                mo += s_a[k * CELLS + cl];
+                mn += s_b[k * CELLS + cl];
+            }
+            q[iA * N + c] = a * mn / mo;
+        }
+    }
 }
 
 }  // namespace bub

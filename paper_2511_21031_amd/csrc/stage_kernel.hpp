@@ -114,6 +114,9 @@ struct StageArgs {
     int ntile[3];
     int nblk_per_xcd;
     int ntiles;
+    int ngroups;        // workgroups per tile, each taking a contiguous range of bpg bins
+    int bpg;            // bins per group (ngroups * bpg >= nb)
+    int nitems;         // ntiles * ngroups
 };
 
 // LDS needs of one tile: coef[F] and scr[SCR] of TF, flag[F] bytes.
@@ -126,9 +129,11 @@ struct StageLds {
 
 // The work of one tile (every thread of the workgroup calls it).
 template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF>
+// Bins b0 <= ib < b1 are this workgroup's; core_out: it also writes the mixture variables
+// (exactly one workgroup per tile does).
 __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, const Phys &ph, const Bins &bins,
-                                           int tile, TF *__restrict__ s_coef, TF *__restrict__ s_scr,
-                                           unsigned char *__restrict__ s_flag)
+                                           int tile, int b0, int b1, bool core_out, TF *__restrict__ s_coef,
+                                           TF *__restrict__ s_scr, unsigned char *__restrict__ s_flag)
 {
     using G = Geo<D, TX_, TY_, TZ_>;
     constexpr int T = G::T, F = G::F, C = G::C, NC = G::NC, NCF = G::NCF, L = G::L;
@@ -278,8 +283,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
 #pragma unroll
     for (int r = 0; r < CPT; ++r) {
         bool ok = tid + r * BLOCK < C;
-        pre_r[r] = ok ? A.qk[(long long)iNR * N + st_g[r]] : 0.0;
-        pre_v[r] = ok ? A.qk[(long long)iNV * N + st_g[r]] : 0.0;
+        pre_r[r] = ok ? A.qk[(long long)(iNR + b0) * N + st_g[r]] : 0.0;
+        pre_v[r] = ok ? A.qk[(long long)(iNV + b0) * N + st_g[r]] : 0.0;
     }
     __syncthreads();
 
@@ -301,7 +306,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
     }
     const double dt = A.rhs_mode ? 0.0 : *A.dtp;
     double own_n = 0.0, own_in = 0.0, own_pl = 0.0, own_irhol = 1.0, own_ic = 1.0;
-    if (active) {
+    if (active && core_out) {
         TF Lc[NCF];
 #pragma unroll
         for (int v = 0; v < NCF; ++v) {
@@ -322,6 +327,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
                 A.qo[o] = r;
             }
         }
+    }
+    if (active) {
         own_n = A.P[PL<D>::N * N + gc];
         own_in = own_n > 0.0 ? frcp(own_n) : 0.0;
         own_pl = A.P[PL<D>::PLQ * N + gc];
@@ -334,7 +341,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
 
     // ---- bins, one at a time: stage -> faces -> cells; next bin's loads overlap the faces ----
     TF *s_R = s_scr, *s_V = s_scr + L, *s_fR = s_scr + 2 * L, *s_fV = s_scr + 2 * L + F;
-    for (int ib = 0; ib < nb; ++ib) {
+    for (int ib = b0; ib < b1; ++ib) {
         const double r0 = bins.r0[ib];
 #pragma unroll
         for (int r = 0; r < CPT; ++r) {
@@ -353,7 +360,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
             }
         }
         __syncthreads();
-        if (ib + 1 < nb) {
+        if (ib + 1 < b1) {
 #pragma unroll
             for (int r = 0; r < CPT; ++r) {
                 bool ok = tid + r * BLOCK < C;
@@ -453,11 +460,14 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs A, Grid g, Phys ph, B
     __shared__ TF s_coef[G::F];
     __shared__ TF s_scr[S::SCR];
     __shared__ unsigned char s_flag[G::F];
-    // XCD-aware tile order: consecutive tiles land on the same XCD (blocks are dealt round-robin).
+    // XCD-aware order: consecutive items land on the same XCD (blocks are dealt round-robin), and
+    // the bin groups of a tile are consecutive items, so they share that XCD's L2.
     const int b = blockIdx.x;
-    const int tile = (b & 7) * A.nblk_per_xcd + (b >> 3);
-    if (tile >= A.ntiles) return;
-    stage_tile<D, TX_, TY_, TZ_, BLOCK, TF>(A, g, ph, bins, tile, s_coef, s_scr, s_flag);
+    const int item = (b & 7) * A.nblk_per_xcd + (b >> 3);
+    if (item >= A.nitems) return;
+    const int tile = item / A.ngroups, grp = item - tile * A.ngroups;
+    const int b0 = grp * A.bpg, b1 = b0 + A.bpg < bins.nb ? b0 + A.bpg : bins.nb;
+    stage_tile<D, TX_, TY_, TZ_, BLOCK, TF>(A, g, ph, bins, tile, b0, b1, grp == 0, s_coef, s_scr, s_flag);
 }
 
 }  // namespace bub

@@ -233,3 +233,26 @@ def test_tile_shapes_give_identical_results(torch, bub, orc, kind):
         assert np.array_equal(o, outs[0])
     best, ms = ctx.autotune(q, reps=2)
     assert ctx.tile == best and 0 <= best < len(ms) and all(m > 0 for m in ms)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("kind", ["c1", "2d_ragged_periodic", "3d_ragged_reflective"])
+def test_bin_groups_give_identical_results(torch, bub, orc, kind, prec):
+    """Splitting a tile's bins over several workgroups leaves every result bitwise unchanged."""
+    case = _case_grid(kind)
+    pb = orc.problem_from_case(case)
+    q0 = _gpu(torch, perturb_bins(orc.init_state(pb, case.prim), case.ndim, case.nb, seed=4))
+    P = bub.PREC_FP64 if prec == "fp64" else bub.PREC_MIXED
+    outs = []
+    for groups in (1, 0, 2, 3, case.nb):
+        ctx = bub.context_from_case(case, precision=P)
+        ctx.set_bin_groups(groups)
+        q = q0.clone()
+        work = ctx.new_work()
+        rhs = ctx.rhs_stage(q)
+        for _ in range(2):
+            ctx.rk3_step(q, work)
+        assert ctx.last_error()[0] == 0
+        outs.append((rhs.cpu().numpy(), q.cpu().numpy()))
+    for r, s in outs[1:]:
+        assert np.array_equal(r, outs[0][0]) and np.array_equal(s, outs[0][1])
