@@ -90,29 +90,33 @@ __device__ inline double frcp(double x)
 }
 
 // WENO5-JS face value at the right face of v2 from v0..v4 (cells i-2..i+2).
-// The three nonlinear weights d_k/(eps+beta_k)^2 are formed as products over
-// the other two indicators so one reciprocal normalises them (FP64 range holds).
+// The nonlinear weights d_k/(eps+beta_k)^2 are normalised through products over
+// the other two indicators, so one reciprocal serves all three (the FP64 range
+// holds them); the linear weights (1/10, 6/10, 3/10) ride on the candidate
+// values, whose 1/6 is folded into their coefficients, and eps into the
+// indicator's last fused multiply-add.
 __device__ inline double weno5(double v0, double v1, double v2, double v3, double v4)
 {
     const double eps = 1e-16;
-    const double c16 = 1.0 / 6.0;
     const double c1312 = 13.0 / 12.0;
-    double q0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) * c16;
-    double q1 = (-v1 + 5.0 * v2 + 2.0 * v3) * c16;
-    double q2 = (2.0 * v2 + 5.0 * v3 - v4) * c16;
-    double d0 = v0 - 2.0 * v1 + v2, e0 = v0 - 4.0 * v1 + 3.0 * v2;
-    double d1 = v1 - 2.0 * v2 + v3, e1 = v1 - v3;
-    double d2 = v2 - 2.0 * v3 + v4, e2 = 3.0 * v2 - 4.0 * v3 + v4;
-    double s0 = eps + (c1312 * d0 * d0 + 0.25 * e0 * e0);
-    double s1 = eps + (c1312 * d1 * d1 + 0.25 * e1 * e1);
-    double s2 = eps + (c1312 * d2 * d2 + 0.25 * e2 * e2);
+    // candidate values: q0 = (2 v0 - 7 v1 + 11 v2)/6, 6 q1 = -v1 + 5 v2 + 2 v3, 3 q2 = (2 v2 + 5 v3 - v4)/2
+    double q0 = fma(1.0 / 3.0, v0, fma(-7.0 / 6.0, v1, (11.0 / 6.0) * v2));
+    double q1x6 = fma(2.0, v3, fma(5.0, v2, -v1));
+    double q2x3 = fma(-0.5, v4, fma(2.5, v3, v2));
+    double d0 = fma(-2.0, v1, v0) + v2, e0 = fma(3.0, v2, fma(-4.0, v1, v0));
+    double d1 = fma(-2.0, v2, v1) + v3, e1 = v1 - v3;
+    double d2 = fma(-2.0, v3, v2) + v4, e2 = fma(-4.0, v3, fma(3.0, v2, v4));
+    double s0 = fma(c1312 * d0, d0, fma(0.25 * e0, e0, eps));
+    double s1 = fma(c1312 * d1, d1, fma(0.25 * e1, e1, eps));
+    double s2 = fma(c1312 * d2, d2, fma(0.25 * e2, e2, eps));
     s0 *= s0;
     s1 *= s1;
     s2 *= s2;
-    double a0 = 0.1 * (s1 * s2);
-    double a1 = 0.6 * (s0 * s2);
-    double a2 = 0.3 * (s0 * s1);
-    return (a0 * q0 + a1 * q1 + a2 * q2) * frcp(a0 + a1 + a2);
+    // a0 : a1 : a2 = 0.1 s1 s2 : 0.6 s0 s2 : 0.3 s0 s1 = p12 : 6 p02 : 3 p01
+    double p12 = s1 * s2, p02 = s0 * s2, p01 = s0 * s1;
+    double num = fma(p12, q0, fma(p02, q1x6, p01 * q2x3));
+    double den = fma(3.0, p01, fma(6.0, p02, p12));
+    return num * frcp(den);
 }
 
 // FP32 WENO5-JS for the mixed form.  The weights are taken in ratio form,

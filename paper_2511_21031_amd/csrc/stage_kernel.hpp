@@ -123,7 +123,10 @@ struct StageArgs {
 template <int D, int TX_, int TY_, int TZ_, typename TF>
 struct StageLds {
     using G = Geo<D, TX_, TY_, TZ_>;
-    static constexpr int SCR = (G::NCF * G::F > 2 * G::L + 2 * G::F) ? G::NCF * G::F : 2 * G::L + 2 * G::F;
+    // line arrays of R and Rdot are LP apart, a multiple of 64 elements, so one paired LDS
+    // access (64-element stride form) serves both
+    static constexpr int LP = (G::L + 63) / 64 * 64;
+    static constexpr int SCR = (G::NCF * G::F > 2 * LP + 2 * G::F) ? G::NCF * G::F : 2 * LP + 2 * G::F;
     static constexpr int BYTES = (G::F + SCR) * (int)sizeof(TF) + G::F;
 };
 
@@ -340,7 +343,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
     __syncthreads();  // s_cf is reused below
 
     // ---- bins, one at a time: stage -> faces -> cells; next bin's loads overlap the faces ----
-    TF *s_R = s_scr, *s_V = s_scr + L, *s_fR = s_scr + 2 * L, *s_fV = s_scr + 2 * L + F;
+    constexpr int LP = StageLds<D, TX_, TY_, TZ_, TF>::LP;
+    TF *s_R = s_scr, *s_V = s_scr + LP, *s_fR = s_scr + 2 * LP, *s_fV = s_scr + 2 * LP + F;
     for (int ib = b0; ib < b1; ++ib) {
         const double r0 = bins.r0[ib];
 #pragma unroll
@@ -382,18 +386,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
                 int p[3] = {fi, fj, fk};
                 p[d] -= 3;
                 const int base = G::template lidx<d>(p[0], p[1], p[2]);
-                TF r6[6], v6[6];
-#pragma unroll
-                for (int o = 0; o < 6; ++o) {
-                    r6[o] = s_R[base + o * S];
-                    v6[o] = s_V[base + o * S];
-                }
-                // upwind side: L uses cells f-3..f+1, R the mirrored f+2..f-2
+                // upwind side only: L reads cells f-3..f+1, R the mirrored f+2..f-2 (a signed stride)
+                const int st = right ? base + 5 * S : base;
+                const int sd = right ? -S : S;
                 TF rr[5], vv[5];
 #pragma unroll
                 for (int o = 0; o < 5; ++o) {
-                    rr[o] = right ? r6[5 - o] : r6[o];
-                    vv[o] = right ? v6[5 - o] : v6[o];
+                    rr[o] = s_R[st + o * sd];
+                    vv[o] = s_V[st + o * sd];
                 }
                 TF RK, VK;
                 if (fl & 2) {
