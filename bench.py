@@ -23,6 +23,10 @@ stream solved one request at a time in plain FP64.  Reports solves/s and the
 p50/p99 latency from arrival to result of both.
 
     python bench.py --workload serving [--requests 512] [--rate 20] [--budget-gib 64] [--no-sequential]
+
+Other workloads: --workload collapse3d (256^3, 21 bins, 10 atm spherical pulse,
+split mode; whole-step throughput in FP64 and mixed precision) and --workload
+lagrangian (192^3 with 1e5 bubbles; bubble steps per second).
 """
 from __future__ import annotations
 
@@ -146,6 +150,80 @@ def serving(args):
     print(json.dumps(out), flush=True)
 
 
+def collapse3d(args):
+    """256^3, 21 bins, 10 atm spherical pulse, split mode: step throughput in FP64 and in the mixed form."""
+    import torch
+    import workloads
+    import paper_2511_21031_amd as bub
+    from paper_2511_21031_amd._binding import K_STAGE
+    torch.cuda.set_device(0)
+    case = workloads.c3()
+    prim = torch.from_numpy(case.prim).cuda()
+    res = {}
+    for name, prec in (("fp64", bub.PREC_FP64), ("mixed", bub.PREC_MIXED)):
+        ctx = bub.context_from_case(case, precision=prec, bubble_mode=bub.BUBBLES_SPLIT)
+        q = ctx.init_state(prim)
+        work = ctx.new_work()
+        best, _ = ctx.autotune(q, work[:q.numel()].view_as(q), reps=2)
+        for _ in range(args.warmup):
+            ctx.rk3_step(q, work)
+        torch.cuda.synchronize()
+        ctx.profile_read(K_STAGE)
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.rk3_step(q, work)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        ctx.profile(False)
+        code = ctx.last_error()[0]
+        sms, sn = ctx.profile_read(K_STAGE)
+        print(f"[collapse3d] {name}: {t / args.steps * 1e3:.1f} ms per step", file=sys.stderr, flush=True)
+        res[name] = {"value": case.ncells * case.nb * 3 * args.steps / t, "ms_per_step": t / args.steps * 1e3,
+                     "k_stage_avg_ms": sms / max(sn, 1), "tile": list(ctx.tiles()[best]), "device_error": code}
+        del q, work, ctx
+        torch.cuda.empty_cache()
+    out = {"metric": "cell·bin RK-stage updates/s", "value": res["mixed"]["value"], "unit": "cell·bin updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["mixed"]["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+           "config": {"workload": "3D 256^3 reflective ensemble-averaged, 21 log-normal bins (sigma 0.3), 10 atm "
+                                  "spherical pulse, split bubble sub-stepping (whole steps, bubble half-steps "
+                                  "included)", "cells": case.ncells, "bins": case.nb},
+           "fp64": res["fp64"], "mixed": res["mixed"], "mixed_over_fp64": res["mixed"]["value"] / res["fp64"]["value"]}
+    print(json.dumps(out), flush=True)
+
+
+def lagrangian(args):
+    """192^3 periodic, 1e5 bubbles, 2 atm plane wave: volume-averaged steps."""
+    import torch
+    import workloads
+    import paper_2511_21031_amd as bub
+    torch.cuda.set_device(0)
+    lc = workloads.c4()
+    ctx = bub.Context(3, lc.n, (lc.dx,) * 3, ((0, 0),) * 3, 1)
+    bg = ctx.lagrangian_bubbles(torch.from_numpy(lc.bubbles).cuda())
+    ql = ctx.lagrangian_init(torch.from_numpy(lc.prim).cuda())
+    aD = ctx.lagrangian_smear(bg)
+    work = ctx.lagrangian_work(lc.nbub)
+    for _ in range(args.warmup):
+        ctx.lagrangian_step(ql, bg, aD, work)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.lagrangian_step(ql, bg, aD, work)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    code = ctx.last_error()[0]
+    out = {"metric": "bubble steps/s", "value": lc.nbub * args.steps / t, "unit": "bubble·steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": t / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "volume-averaged 192^3 periodic, 1e5 bubbles in the central half box, R0 lognormal "
+                                  "about 10 um (sigma 0.3), 2 atm plane wave, DP5(4) bubble sub-steps",
+                      "cells": lc.ncells, "bubbles": lc.nbub},
+           "cell_stage_updates_per_s": lc.ncells * 3 * args.steps / t, "device_error": code}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,7 +233,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
-    ap.add_argument("--workload", choices=["stage", "serving"], default="stage")
+    ap.add_argument("--workload", choices=["stage", "serving", "collapse3d", "lagrangian"], default="stage")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--rate", type=float, default=20.0, help="serving: mean arrivals per second")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: HBM budget for resident solves")
@@ -169,6 +247,12 @@ def main():
         sys.exit(2)
     if args.workload == "serving":
         serving(args)
+        return
+    if args.workload == "collapse3d":
+        collapse3d(args)
+        return
+    if args.workload == "lagrangian":
+        lagrangian(args)
         return
 
     import torch
