@@ -107,7 +107,8 @@ def serving(args):
     torch.cuda.synchronize()
 
     budget = int(args.budget_gib * (1 << 30))
-    srv = Server(budget, max_slots=64, precision=bub.PREC_MIXED, bubble_mode=bub.BUBBLES_SPLIT, chunk=10)
+    srv = Server(budget, max_slots=64, precision=bub.PREC_MIXED, bubble_mode=bub.BUBBLES_SPLIT, chunk=10,
+                 lanes=args.lanes)
     ts = 0.0 if args.burst else 1.0
     recs = srv.run(reqs, workloads.request_case, time_scale=ts, progress=progress("served"))
     t_srv = max(r.finished for r in recs)
@@ -130,7 +131,8 @@ def serving(args):
                                + ("all arriving at t=0" if args.burst else f"Poisson arrivals at {args.rate}/s")
                                + f" (70% 1D 200-4000 cells, 25% 2D 64^2-512^2, 5% 3D 96^3; 11/21/31 "
                                f"bins; 50-500 steps), split bubble sub-stepping, mixed precision",
-                   "hbm_budget_gib": args.budget_gib, "max_slots": 64, "chunk": 10,
+                   "hbm_budget_gib": args.budget_gib, "max_slots": 64, "chunk": 10, "lanes": args.lanes,
+                   "hw_queues": args.hw_queues or "HIP default",
                    "cell_bin_rk_steps": cell_bin_steps},
         "serving": {"p50_s": s_srv["p50_s"], "p99_s": s_srv["p99_s"], "mean_s": s_srv["mean_s"],
                     "wall_s": t_srv, "errors": s_srv["errors"], "peak_resident": srv.peak_active,
@@ -239,6 +241,9 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: HBM budget for resident solves")
     ap.add_argument("--no-sequential", action="store_true", help="serving: skip the sequential FP64 baseline")
     ap.add_argument("--burst", action="store_true", help="serving: every request arrives at t = 0")
+    ap.add_argument("--lanes", type=int, default=4, help="serving: batch streams")
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="serving: hardware queues per process (HIP GPU_MAX_HW_QUEUES, at most 32; 0 = HIP default)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -246,6 +251,10 @@ def main():
               "multi-GPU path (run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
     if args.workload == "serving":
+        if args.hw_queues:
+            if not 1 <= args.hw_queues <= 32:
+                sys.exit("--hw-queues must be in 1..32")
+            os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)   # read when HIP initialises
         serving(args)
         return
     if args.workload == "collapse3d":

@@ -241,6 +241,20 @@ int bub_batch_remove(bub_batch *batch, int slot);
 /* nsteps steps of every member, ordered on `stream` (no host synchronisation). */
 int bub_batch_step(bub_batch *batch, int nsteps, void *stream);
 
+/* Number of internal streams ("lanes", 1..16, default 4) the members are dealt
+ * over.  Kernels of different lanes run concurrently only as far as the
+ * process has hardware queues (HIP's GPU_MAX_HW_QUEUES, 4 by default), so more
+ * lanes pay only with more queues.  BUB_EINVAL outside 1..16. */
+int bub_batch_lanes(bub_batch *batch, int lanes);
+
+/* Graph mode (on by default): each member's step is captured once as a HIP
+ * graph (its kernels only) and replayed with one graph launch per step, which
+ * cuts the host's launch work about tenfold; a member is captured again when
+ * its tile shape or bin grouping changes, and profiled members launch
+ * directly.  enable = 0 launches every kernel directly.  Results are the same
+ * either way. */
+int bub_batch_graphs(bub_batch *batch, int enable);
+
 /* Members, total cells and total cell-bins of the current members. */
 int bub_batch_info(const bub_batch *batch, int *ncases, int64_t *cells, int64_t *cell_bins);
 

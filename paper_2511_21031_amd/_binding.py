@@ -90,6 +90,8 @@ _SIGS = {
     "bub_batch_step": [_vp, ctypes.c_int, _vp],
     "bub_batch_info": [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
     "bub_batch_autotune": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _vp],
+    "bub_batch_lanes": [_vp, ctypes.c_int],
+    "bub_batch_graphs": [_vp, ctypes.c_int],
     "bub_profile": [_vp, ctypes.c_int],
     "bub_profile_read": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)],
 }
@@ -408,6 +410,14 @@ class Batch:
         n, c, cb = ctypes.c_int(), _i64(), _i64()
         _check(lib().bub_batch_info(self._h, ctypes.byref(n), ctypes.byref(c), ctypes.byref(cb)), "bub_batch_info")
         return n.value, c.value, cb.value
+
+    def set_graphs(self, enable: bool):
+        """Replay each member's step as a captured graph (default) or launch its kernels directly."""
+        _check(lib().bub_batch_graphs(self._h, int(bool(enable))), "bub_batch_graphs")
+
+    def set_lanes(self, lanes: int):
+        """Internal streams the members are dealt over (1..16)."""
+        _check(lib().bub_batch_lanes(self._h, int(lanes)), "bub_batch_lanes")
 
     def autotune(self, reps: int = 3, stream=None) -> int:
         """Tune the stage tile shape of every new (ndim, nb) class; returns the number of tuned classes."""

@@ -931,10 +931,16 @@ struct bub_batch {
         bub_ctx *ctx = nullptr;
         double *q = nullptr, *work = nullptr;
         bool used = false;
+        hipGraphExec_t exec = nullptr;   // one captured rk3_step of this member (graph mode)
+        int cap_tile = -1, cap_groups = -1;
     };
     int precision = 0;
+    bool graphs = true;                           // replay each member's step as one captured graph
+    hipStream_t cap = nullptr;                    // capture stream (never executes work)
+    std::vector<hipGraphExec_t> retired;          // graphs of removed members, freed once the lanes are idle
     std::vector<Member> slots;
-    static constexpr int NSTREAM = 4;             // one per hardware queue a process gets by default
+    static constexpr int NSTREAM = 16;            // internal streams (lanes) created
+    int lanes = 4;                                // lanes used: one per hardware queue a process gets by default
     hipStream_t st[NSTREAM] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t join[NSTREAM] = {};
@@ -953,6 +959,41 @@ int batch_class_tile(const bub_batch *b, const bub_ctx *c)
 
 }  // namespace
 
+namespace {
+
+// Capture one rk3_step of member m (its kernels only: no copies, no memsets) into a graph.
+int batch_capture(bub_batch *b, bub_batch::Member &m)
+{
+    hipGraph_t g = nullptr;
+    HIP_OK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = bub_rk3_step(m.ctx, m.q, m.work, 0.0, nullptr, b->cap);
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (rc || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : BUB_EHIP;
+    }
+    hipGraphExec_t x = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return BUB_EHIP;
+    if (m.exec) b->retired.push_back(m.exec);
+    m.exec = x;
+    m.cap_tile = m.ctx->tile;
+    m.cap_groups = m.ctx->bin_groups;
+    return BUB_OK;
+}
+
+int batch_free_retired(bub_batch *b)
+{
+    for (int k = 0; k < bub_batch::NSTREAM; ++k)
+        if (b->st[k]) HIP_OK(hipStreamSynchronize(b->st[k]));
+    for (hipGraphExec_t x : b->retired) (void)hipGraphExecDestroy(x);
+    b->retired.clear();
+    return BUB_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int bub_batch_create(int precision, int max_cases, bub_batch **out)
@@ -962,7 +1003,8 @@ int bub_batch_create(int precision, int max_cases, bub_batch **out)
     if (!b) return BUB_ENOMEM;
     b->precision = precision;
     b->slots.resize(max_cases);
-    bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+    bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess &&
+              hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess;
     for (int k = 0; k < bub_batch::NSTREAM && ok; ++k)
         ok = hipStreamCreateWithFlags(&b->st[k], hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) == hipSuccess;
@@ -977,13 +1019,14 @@ int bub_batch_create(int precision, int max_cases, bub_batch **out)
 int bub_batch_destroy(bub_batch *b)
 {
     if (!b) return BUB_EINVAL;
+    (void)batch_free_retired(b);
+    for (auto &m : b->slots)
+        if (m.exec) (void)hipGraphExecDestroy(m.exec);
     for (int k = 0; k < bub_batch::NSTREAM; ++k) {
-        if (b->st[k]) {
-            (void)hipStreamSynchronize(b->st[k]);
-            (void)hipStreamDestroy(b->st[k]);
-        }
+        if (b->st[k]) (void)hipStreamDestroy(b->st[k]);
         if (b->join[k]) (void)hipEventDestroy(b->join[k]);
     }
+    if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->fork) (void)hipEventDestroy(b->fork);
     delete b;
     return BUB_OK;
@@ -1018,6 +1061,7 @@ int bub_batch_add(bub_batch *b, bub_ctx *c, double *q, double *work, int *slot)
 int bub_batch_remove(bub_batch *b, int slot)
 {
     if (!b || slot < 0 || slot >= (int)b->slots.size() || !b->slots[slot].used) return BUB_EINVAL;
+    if (b->slots[slot].exec) b->retired.push_back(b->slots[slot].exec);   // launches may still be in flight
     b->slots[slot] = bub_batch::Member{};
     return BUB_OK;
 }
@@ -1054,12 +1098,25 @@ int bub_batch_step(bub_batch *b, int nsteps, void *stream)
     std::vector<int> lane(b->slots.size(), 0);
     for (int i : order) {
         int k = 0;
-        for (int j = 1; j < bub_batch::NSTREAM; ++j)
+        for (int j = 1; j < b->lanes; ++j)
             if (load[j] < load[k]) k = j;
         lane[i] = k;
         load[k] += work_of(i);
     }
-    const int used = (int)std::min<size_t>(order.size(), bub_batch::NSTREAM);
+    const int used = (int)std::min<size_t>(order.size(), (size_t)b->lanes);
+    if (b->retired.size() >= 64) {   // rare: wait for the lanes, then free removed members' graphs
+        int rc = batch_free_retired(b);
+        if (rc) return rc;
+    }
+    if (b->graphs)
+        for (int i : order) {
+            auto &m = b->slots[i];
+            if (m.ctx->prof_on) continue;   // timed members launch directly
+            if (!m.exec || m.cap_tile != m.ctx->tile || m.cap_groups != m.ctx->bin_groups) {
+                int rc = batch_capture(b, m);
+                if (rc) return rc;
+            }
+        }
     // fork: every lane starts after the work already queued on the caller's stream
     HIP_OK(hipEventRecord(b->fork, s));
     for (int k = 0; k < used; ++k) HIP_OK(hipStreamWaitEvent(b->st[k], b->fork, 0));
@@ -1067,14 +1124,32 @@ int bub_batch_step(bub_batch *b, int nsteps, void *stream)
     for (int step = 0; step < nsteps; ++step)
         for (int i : order) {
             auto &m = b->slots[i];
-            int rc = bub_rk3_step(m.ctx, m.q, m.work, 0.0, nullptr, b->st[lane[i]]);
-            if (rc) return rc;
+            if (b->graphs && m.exec && !m.ctx->prof_on) {
+                HIP_OK(hipGraphLaunch(m.exec, b->st[lane[i]]));
+            } else {
+                int rc = bub_rk3_step(m.ctx, m.q, m.work, 0.0, nullptr, b->st[lane[i]]);
+                if (rc) return rc;
+            }
         }
     // join: the caller's stream continues after every lane
     for (int k = 0; k < used; ++k) {
         HIP_OK(hipEventRecord(b->join[k], b->st[k]));
         HIP_OK(hipStreamWaitEvent(s, b->join[k], 0));
     }
+    return BUB_OK;
+}
+
+int bub_batch_graphs(bub_batch *b, int enable)
+{
+    if (!b) return BUB_EINVAL;
+    b->graphs = enable != 0;
+    return BUB_OK;
+}
+
+int bub_batch_lanes(bub_batch *b, int lanes)
+{
+    if (!b || lanes < 1 || lanes > bub_batch::NSTREAM) return BUB_EINVAL;
+    b->lanes = lanes;
     return BUB_OK;
 }
 

@@ -66,7 +66,8 @@ class Server:
     """Continuous batching of ensemble-averaged solves under an HBM budget (bytes)."""
 
     def __init__(self, hbm_budget: int, max_slots: int = 64, precision=None, bubble_mode=None,
-                 chunk: int = 10, keep_results: bool = False, autotune: bool = True, footprint=footprint_bytes):
+                 chunk: int = 10, keep_results: bool = False, autotune: bool = True, footprint=footprint_bytes,
+                 lanes: int = 4):
         self.budget = int(hbm_budget)
         self.max_slots = int(max_slots)
         self.precision = precision
@@ -75,6 +76,7 @@ class Server:
         self.keep_results = keep_results
         self.autotune = autotune
         self.footprint = footprint
+        self.lanes = int(lanes)
         self.used = 0
         self.peak_used = 0
         self.peak_active = 0
@@ -93,6 +95,7 @@ class Server:
             self.bubble_mode = BUBBLES_SPLIT
         self.stream = torch.cuda.Stream()
         self.batch = Batch(self.precision, self.max_slots)
+        self.batch.set_lanes(self.lanes)
 
     def _admit(self, rec: Record, case) -> int:
         import torch

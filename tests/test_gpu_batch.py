@@ -59,10 +59,14 @@ def _alone(torch, bub, case, split, prec, steps):
     return q
 
 
-def _join(torch, bub, batch, case, split, prec):
+def _fresh(torch, bub, case, split, prec):
     ctx = bub.context_from_case(case, precision=prec, bubble_mode=bub.BUBBLES_SPLIT if split else bub.BUBBLES_UNSPLIT)
     q = ctx.init_state(_gpu(torch, case.prim))
-    work = ctx.new_work()
+    return ctx, q, ctx.new_work()
+
+
+def _join(torch, bub, batch, case, split, prec):
+    ctx, q, work = _fresh(torch, bub, case, split, prec)
     return batch.add(ctx, q, work), (ctx, q, work)
 
 
@@ -101,12 +105,14 @@ def test_batch_members_bitwise_equal_alone(torch, bub, prec):
     batch.close()
 
 
+@pytest.mark.parametrize("graphs", [True, False])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_stream_batch_members_bitwise_equal_alone(torch, bub, prec):
+def test_stream_batch_members_bitwise_equal_alone(torch, bub, prec, graphs):
     """Members join and leave a running batch; each ends bitwise equal to its problem stepped alone."""
     P = bub.PREC_FP64 if prec == "fp64" else bub.PREC_MIXED
     mem = _members()
     batch = bub.Batch(P, max_cases=8)
+    batch.set_graphs(graphs)
     slots, held, steps = {}, {}, {}
     for name, case, split in mem[:4]:
         slots[name], held[name] = _join(torch, bub, batch, case, split, P)
@@ -153,6 +159,25 @@ def test_stream_batch_class_autotune(torch, bub):
     for name, case, split in mem[:4]:
         assert torch.equal(held[name][1], _alone(torch, bub, case, split, P, 2)), name
     assert torch.equal(late[1], _alone(torch, bub, late_case, late_split, P, 2))
+    batch.close()
+
+
+def test_graph_replays_match_eager_steps(torch, bub):
+    """Every replay of the captured member steps, with eager work and host syncs in between,
+    matches a twin of each member stepped eagerly, bitwise."""
+    P = bub.PREC_FP64
+    mem = _members()
+    batch = bub.Batch(P, max_cases=8)
+    held = [_join(torch, bub, batch, case, split, P)[1] for _, case, split in mem]
+    twins = [_fresh(torch, bub, case, split, P) for _, case, split in mem]
+    for rnd in range(4):
+        batch.step(1)
+        torch.cuda.synchronize()
+        for (ctx, q, work) in twins:          # eager work between the replays
+            ctx.rk3_step(q, work)
+        torch.cuda.synchronize()
+        for (_, q, _), (_, qt, _) in zip(held, twins):
+            assert torch.equal(q, qt), rnd
     batch.close()
 
 
