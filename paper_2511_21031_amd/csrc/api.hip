@@ -96,7 +96,13 @@ template <> struct Tile<2, 3> { static constexpr int TX = 32, TY = 16, TZ = 1, B
 template <> struct Tile<3, 0> { static constexpr int TX = 8, TY = 8, TZ = 4, BLOCK = 256; };
 template <> struct Tile<3, 1> { static constexpr int TX = 16, TY = 4, TZ = 4, BLOCK = 256; };
 template <> struct Tile<3, 2> { static constexpr int TX = 8, TY = 4, TZ = 4, BLOCK = 128; };
-constexpr int TILE_COUNT[4] = {0, 3, 4, 3};
+// Balanced shapes: at most one face per thread in every direction ((TX+1) TY TZ <= BLOCK, ...),
+// so no wave carries extra face work into the barrier that follows the face phase.
+template <> struct Tile<2, 4> { static constexpr int TX = 32, TY = 15, TZ = 1, BLOCK = 512; };
+template <> struct Tile<2, 5> { static constexpr int TX = 16, TY = 15, TZ = 1, BLOCK = 256; };
+template <> struct Tile<3, 3> { static constexpr int TX = 8, TY = 8, TZ = 3, BLOCK = 256; };
+template <> struct Tile<3, 4> { static constexpr int TX = 8, TY = 8, TZ = 7, BLOCK = 512; };
+constexpr int TILE_COUNT[4] = {0, 3, 6, 5};
 
 template <int D, int V>
 void tile_info(int *tx, int *ty, int *tz, int *block)
@@ -231,10 +237,14 @@ int stage(bub_ctx *c, const StageArgs &A, hipStream_t s)
         if (v == 1) return launch_stage_v<2, 1>(c, A, s);
         if (v == 2) return launch_stage_v<2, 2>(c, A, s);
         if (v == 3) return launch_stage_v<2, 3>(c, A, s);
+        if (v == 4) return launch_stage_v<2, 4>(c, A, s);
+        if (v == 5) return launch_stage_v<2, 5>(c, A, s);
         return launch_stage_v<2, 0>(c, A, s);
     default:
         if (v == 1) return launch_stage_v<3, 1>(c, A, s);
         if (v == 2) return launch_stage_v<3, 2>(c, A, s);
+        if (v == 3) return launch_stage_v<3, 3>(c, A, s);
+        if (v == 4) return launch_stage_v<3, 4>(c, A, s);
         return launch_stage_v<3, 0>(c, A, s);
     }
 }
@@ -821,9 +831,13 @@ int bub_tile_info(const bub_ctx *c, int idx, int *tx, int *ty, int *tz, int *blo
     case 21: tile_info<2, 1>(tx, ty, tz, block); break;
     case 22: tile_info<2, 2>(tx, ty, tz, block); break;
     case 23: tile_info<2, 3>(tx, ty, tz, block); break;
+    case 24: tile_info<2, 4>(tx, ty, tz, block); break;
+    case 25: tile_info<2, 5>(tx, ty, tz, block); break;
     case 30: tile_info<3, 0>(tx, ty, tz, block); break;
     case 31: tile_info<3, 1>(tx, ty, tz, block); break;
-    default: tile_info<3, 2>(tx, ty, tz, block); break;
+    case 32: tile_info<3, 2>(tx, ty, tz, block); break;
+    case 33: tile_info<3, 3>(tx, ty, tz, block); break;
+    default: tile_info<3, 4>(tx, ty, tz, block); break;
     }
     return BUB_OK;
 }

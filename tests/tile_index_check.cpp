@@ -194,9 +194,13 @@ int main()
     check_2d<31, 8>();
     check_2d<64, 4>();
     check_2d<32, 16>();
+    check_2d<32, 15>();
+    check_2d<16, 15>();
     check_3d<8, 8, 4>();
     check_3d<16, 4, 4>();
     check_3d<8, 4, 4>();
+    check_3d<8, 8, 3>();
+    check_3d<8, 8, 7>();
     std::printf("%s (%d failures)\n", failures ? "FAIL" : "OK", failures);
     return failures ? 1 : 0;
 }
