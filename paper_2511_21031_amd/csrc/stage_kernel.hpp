@@ -343,10 +343,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
     __syncthreads();  // s_cf is reused below
 
     // ---- bins, one at a time: stage -> faces -> cells; next bin's loads overlap the faces ----
+    // The owned cell is slot 0 of this thread's staging plan (cross index tid < T), so its own
+    // bin values of u^(k) arrive with the staging loads; its u^n values are fetched one bin ahead too.
+    const bool own_un = active && !A.rhs_mode && A.a != 0.0;
+    double pre_nr = own_un ? A.qn[(long long)(iNR + b0) * N + gc] : 0.0;
+    double pre_nv = own_un ? A.qn[(long long)(iNV + b0) * N + gc] : 0.0;
     constexpr int LP = StageLds<D, TX_, TY_, TZ_, TF>::LP;
     TF *s_R = s_scr, *s_V = s_scr + LP, *s_fR = s_scr + 2 * LP, *s_fV = s_scr + 2 * LP + F;
     for (int ib = b0; ib < b1; ++ib) {
         const double r0 = bins.r0[ib];
+        const double own_r = pre_r[0], own_v = pre_v[0], own_nr = pre_nr, own_nv = pre_nv;
 #pragma unroll
         for (int r = 0; r < CPT; ++r) {
             if (tid + r * BLOCK < C) {
@@ -365,6 +371,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
         }
         __syncthreads();
         if (ib + 1 < b1) {
+            if (own_un) {
+                pre_nr = A.qn[(long long)(iNR + ib + 1) * N + gc];
+                pre_nv = A.qn[(long long)(iNV + ib + 1) * N + gc];
+            }
 #pragma unroll
             for (int r = 0; r < CPT; ++r) {
                 bool ok = tid + r * BLOCK < C;
@@ -425,7 +435,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
             }
             double LR = (double)LRf, LV = (double)LVf;
             long long oR = (long long)(iNR + ib) * N + gc, oV = (long long)(iNV + ib) * N + gc;
-            const double xr0 = A.qk[oR], xv0 = A.qk[oV];
+            const double xr0 = own_r, xv0 = own_v;   // = A.qk[oR], A.qk[oV]
             if (A.sources && own_n > 0.0) {
                 // Keller--Miksis in FP64 from the FP64 state of the owned cell
                 double own_R = xr0 * own_in, own_V = xv0 * own_in;
@@ -439,8 +449,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
                 double xr = A.b * (xr0 + dt * LR);
                 double xv = A.b * (xv0 + dt * LV);
                 if (A.a != 0.0) {
-                    xr += A.a * A.qn[oR];
-                    xv += A.a * A.qn[oV];
+                    xr += A.a * own_nr;   // = A.qn[oR]
+                    xv += A.a * own_nv;
                 }
                 A.qo[oR] = xr;
                 A.qo[oV] = xv;
