@@ -280,7 +280,13 @@ struct BinTable {
 __global__ void k_ctx_init(double *bins, BinTable t, int n, Scalars *sc)
 {
     for (int i = threadIdx.x; i < n; i += blockDim.x) bins[i] = t.v[i];
-    if (threadIdx.x == 0) *sc = Scalars{};
+    for (int i = threadIdx.x; i < WMAX_SLOTS * WMAX_STRIDE; i += blockDim.x) sc->wmax[i] = 0ull;
+    if (threadIdx.x == 0) {
+        sc->dt = 0.0;
+        sc->err_code = 0;
+        sc->err_bin = 0;
+        sc->err_cell = 0;
+    }
 }
 
 __global__ void k_err_copy(const Scalars *sc, int64_t *dst)
@@ -557,7 +563,7 @@ int bub_rk3_step(bub_ctx *c, double *q, double *work, double dt, double *dt_dev,
     int rc = prim(c, q, c->d_P, cfl ? PRIM_CFL : PRIM_ONLY, s);
     if (rc) return rc;
     long pr = prof_begin(c, BUB_K_OTHER, s);
-    hipLaunchKernelGGL(k_dt, dim3(1), dim3(1), 0, s, c->d_sc, cfl ? 0.0 : dt, c->opts.cfl, dt_dev);
+    hipLaunchKernelGGL(k_dt, dim3(1), dim3(WMAX_SLOTS), 0, s, c->d_sc, cfl ? 0.0 : dt, c->opts.cfl, dt_dev);
     prof_end(c, pr, s);
     HIP_OK(hipGetLastError());
     if (split) {
@@ -753,7 +759,7 @@ int bub_lagrangian_step(bub_ctx *c, double *ql, double *bubbles, int64_t nbub, d
     double *w1 = work, *w2 = work + 5 * g.N, *forcing = work + 10 * g.N;
     const bool cfl = !(dt > 0.0);
     if ((rc = el_prim(c, g, ql, cfl, s))) return rc;
-    hipLaunchKernelGGL(k_dt, dim3(1), dim3(1), 0, s, c->d_sc, cfl ? 0.0 : dt, c->opts.cfl, dt_dev);
+    hipLaunchKernelGGL(k_dt, dim3(1), dim3(WMAX_SLOTS), 0, s, c->d_sc, cfl ? 0.0 : dt, c->opts.cfl, dt_dev);
     if (nsub && nbub > 0) hipLaunchKernelGGL(k_fill_i, dim3(blocks_for(nbub)), dim3(256), 0, s, nsub, (long long)nbub);
     const double *dtp = &c->d_sc->dt;
     if ((rc = el_bubbles(c, g, bubbles, nbub, forcing, dtp, 0.5, nsub, s))) return rc;

@@ -39,14 +39,32 @@ struct Bins {
     double m3_eq;  // sum w r0^3
 };
 
+// The wave-speed max is gathered in WMAX_SLOTS partial maxima, one per 128-byte line, each
+// workgroup posting to slot blockIdx % WMAX_SLOTS: with one counter, the one atomic per wave of
+// a large grid (10^5 waves) queues at a single address.
+constexpr int WMAX_SLOTS = 64, WMAX_STRIDE = 16;
+
 // Device scalars of one context.
 struct Scalars {
-    unsigned long long wmax;  // bit pattern of max (|u_d| + c)/dx_d (positive double)
     double dt;                // step used by the last rk3_step
     int err_code;             // sticky first error (0 = none)
     int err_bin;
     long long err_cell;
+    long long pad_[13];
+    // bit patterns of partial maxima of (|u_d| + c)/dx_d (positive doubles order as integers)
+    unsigned long long wmax[WMAX_SLOTS * WMAX_STRIDE];
 };
+
+// Wavefront max of the CFL wave speed, then one atomic per wave into this workgroup's slot.
+__device__ inline void wmax_post(double w, Scalars *sc)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(w, off, 64);
+        w = o > w ? o : w;
+    }
+    if ((threadIdx.x & 63) == 0 && w > 0.0)
+        atomicMax(&sc->wmax[(blockIdx.x % WMAX_SLOTS) * WMAX_STRIDE], (unsigned long long)__double_as_longlong(w));
+}
 
 enum { E_NONFINITE = -4, E_NEGR = -5, E_SUBSTEP = -6 };
 

@@ -140,13 +140,8 @@ __device__ __forceinline__ double prim_finish(const double *__restrict__ q, doub
     return wmax;
 }
 
-// Wavefront max of the CFL wave speed, then one atomic per wave on the bit
-// pattern (positive doubles order as unsigned integers).
-__device__ inline void cfl_reduce(double wmax, Scalars *sc)
-{
-    for (int off = 32; off > 0; off >>= 1) wmax = dmax(wmax, __shfl_xor(wmax, off, 64));
-    if ((threadIdx.x & 63) == 0 && wmax > 0.0) atomicMax(&sc->wmax, (unsigned long long)__double_as_longlong(wmax));
-}
+// Wavefront max of the CFL wave speed, posted to the workgroup's partial-max slot.
+__device__ inline void cfl_reduce(double wmax, Scalars *sc) { wmax_post(wmax, sc); }
 
 // Primitive pass; grid = ceil(N / CELLS) workgroups of CELLS * S threads.  A workgroup owns CELLS
 // consecutive cells; thread (cell, slot) sums the bins slot, slot + S, ... (each wave reads
@@ -243,14 +238,23 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ prim, d
     }
 }
 
-// Time step from the wave-speed max (or a fixed value); clears the max for the next step.
-__global__ void k_dt(Scalars *sc, double fixed_dt, double cfl, double *user_dt)
+// Time step from the wave-speed max (or a fixed value); clears the partial maxima for the next
+// step.  One wave of WMAX_SLOTS threads.
+__global__ void __launch_bounds__(WMAX_SLOTS) k_dt(Scalars *sc, double fixed_dt, double cfl, double *user_dt)
 {
-    double dt = fixed_dt;
-    if (!(dt > 0.0)) dt = cfl / __longlong_as_double((long long)sc->wmax);
-    sc->dt = dt;
-    sc->wmax = 0ull;
-    if (user_dt) *user_dt = dt;
+    const int i = threadIdx.x;
+    unsigned long long m = sc->wmax[i * WMAX_STRIDE];
+    sc->wmax[i * WMAX_STRIDE] = 0ull;
+    for (int off = WMAX_SLOTS / 2; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(m, off, 64);
+        m = o > m ? o : m;
+    }
+    if (i == 0) {
+        double dt = fixed_dt;
+        if (!(dt > 0.0)) dt = cfl / __longlong_as_double((long long)m);
+        sc->dt = dt;
+        if (user_dt) *user_dt = dt;
+    }
 }
 
 

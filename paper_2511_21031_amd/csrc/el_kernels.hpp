@@ -101,11 +101,7 @@ __global__ void __launch_bounds__(256) k_el_prim(const double *__restrict__ ql, 
             for (int d = 0; d < 3; ++d) wmax = dmax(wmax, (fabs(u[d]) + cs) * g.inv_dx);
         }
     }
-    if (CFL) {
-        for (int off = 32; off > 0; off >>= 1) wmax = dmax(wmax, __shfl_xor(wmax, off, 64));
-        if ((threadIdx.x & 63) == 0 && wmax > 0.0)
-            atomicMax(&sc->wmax, (unsigned long long)__double_as_longlong(wmax));
-    }
+    if (CFL) wmax_post(wmax, sc);
 }
 
 // Host cell of a bubble coordinate and the kernel support half-width in cells.
