@@ -45,10 +45,14 @@ VALU_PEAK_WAVE_INSTS = 256 * 2.4e9       # 256 CUs x 2.4 GHz x one wave64 VALU i
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_2d1024_nb31_traffic.md")
 
 
+# the sources that define the stage kernel's code (tile shapes are part of the kernel's name)
+STAGE_SOURCES = ("device_common.hpp", "ee_kernels.hpp", "stage_kernel.hpp")
+
+
 def kernel_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_21031_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in STAGE_SOURCES:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

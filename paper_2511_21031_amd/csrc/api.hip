@@ -659,7 +659,9 @@ int el_bubbles(bub_ctx *c, const ElGrid &g, double *b, long long nb, double *for
 int el_stage(bub_ctx *c, const ElGrid &g, ElStageArgs A, hipStream_t s)
 {
     long pr = prof_begin(c, BUB_K_STAGE, s);
-    hipLaunchKernelGGL(k_el_stage, dim3(blocks_for(g.N)), dim3(256), 0, s, A, g, c->ph);
+    const int ntx = (g.n[0] + ELT_X - 1) / ELT_X, nty = (g.n[1] + ELT_Y - 1) / ELT_Y;
+    const int ntz = (g.n[2] + ELT_Z - 1) / ELT_Z;
+    hipLaunchKernelGGL(k_el_stage, dim3((unsigned)ntx * nty * ntz), dim3(ELT_BLOCK), 0, s, A, g, c->ph, ntx, nty);
     prof_end(c, pr, s);
     return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
 }

@@ -9,9 +9,9 @@
 //                Dormand--Prince 5(4) sub-steps, forcing frozen.
 //  k_el_scatter  one wavefront per bubble: volume and volume rate smeared with
 //                the kernel (eq. kernel3D) by FP64 atomic adds.
-//  k_el_stage    one thread per cell: WENO5 + HLLC fluxes of the liquid
-//                (stiffened gas), the bubble source terms with alpha and its
-//                rate frozen, RK combine.
+//  k_el_stage    a workgroup per tile of cells: WENO5 + HLLC fluxes of the
+//                liquid (stiffened gas), each face once, through LDS; the
+//                bubble source terms with alpha and its rate frozen; RK combine.
 #pragma once
 
 #include <type_traits>
@@ -359,42 +359,72 @@ __device__ inline void el_face(const double *__restrict__ P, const ElGrid &g, co
     uR = WR[1 + d];
 }
 
-__global__ void __launch_bounds__(256) k_el_stage(ElStageArgs A, ElGrid g, Phys ph)
+// Tile of the liquid stage: TX x TY x TZ cells, one thread per cell, every face of the tile computed
+// once (the faces of direction d form the box T + e_d; at most one per thread in each direction).
+constexpr int ELT_X = 8, ELT_Y = 8, ELT_Z = 3, ELT_BLOCK = 256;
+
+__global__ void __launch_bounds__(ELT_BLOCK) k_el_stage(ElStageArgs A, ElGrid g, Phys ph, int ntx, int nty)
 {
+    constexpr int TX = ELT_X, TY = ELT_Y, TZ = ELT_Z, T = TX * TY * TZ;
+    constexpr int FMAX = TX * TY * (TZ + 1) > (TX + 1) * TY * TZ ? TX * TY * (TZ + 1) : (TX + 1) * TY * TZ;
+    __shared__ double s_f[9][FMAX];   // per face: flux[5], p_L, p_R, u_L, u_R
     const long long N = g.N;
+    const int tid = threadIdx.x;
+    const int tile = blockIdx.x;
+    const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
+    const int li = tid % TX, lj = (tid / TX) % TY, lk = tid / (TX * TY);
+    const int co[3] = {x0 + li, y0 + lj, z0 + lk};
+    const bool active = tid < T && co[0] < g.n[0] && co[1] < g.n[1] && co[2] < g.n[2];
+    const long long c = (long long)co[0] + (long long)g.n[0] * ((long long)co[1] + (long long)g.n[1] * co[2]);
     const double dt = A.rhs_mode ? 0.0 : *A.dtp;
-    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
-        int co[3] = {(int)(c % g.n[0]), (int)((c / g.n[0]) % g.n[1]), (int)(c / ((long long)g.n[0] * g.n[1]))};
-        double L[5] = {0, 0, 0, 0, 0}, gradp[3], divpu = 0.0;
-        auto dir = [&](auto dtag) {
-            constexpr int d = decltype(dtag)::value;
-            int hi[3] = {co[0], co[1], co[2]};
-            hi[d] += 1;
-            double Fl[5], Fh[5], pl0, pr0, ul0, ur0, pl1, pr1, ul1, ur1;
-            el_face<d>(A.P, g, ph, co, Fl, pl0, pr0, ul0, ur0);
-            el_face<d>(A.P, g, ph, hi, Fh, pl1, pr1, ul1, ur1);
+    double L[5] = {0, 0, 0, 0, 0}, gradp[3] = {0, 0, 0}, divpu = 0.0;
+    auto dir = [&](auto dtag) {
+        constexpr int d = decltype(dtag)::value;
+        constexpr int BX = TX + (d == 0), BY = TY + (d == 1), BZ = TZ + (d == 2), FD = BX * BY * BZ;
+        for (int t = tid; t < FD; t += ELT_BLOCK) {
+            const int f[3] = {x0 + t % BX, y0 + (t / BX) % BY, z0 + t / (BX * BY)};
+            // faces of cells outside the grid are not needed (the face at n[d] closes the last cell)
+            bool need = true;
+            for (int e = 0; e < 3; ++e) need = need && (e == d ? f[e] <= g.n[e] : f[e] < g.n[e]);
+            if (!need) continue;
+            double F[5], pl, pr, ul, ur;
+            el_face<d>(A.P, g, ph, f, F, pl, pr, ul, ur);
+            for (int k = 0; k < 5; ++k) s_f[k][t] = F[k];
+            s_f[5][t] = pl;
+            s_f[6][t] = pr;
+            s_f[7][t] = ul;
+            s_f[8][t] = ur;
+        }
+        __syncthreads();
+        if (active) {
+            const int lo = li + BX * (lj + BY * lk);
+            const int hi = lo + (d == 0 ? 1 : (d == 1 ? BX : BX * BY));
 #pragma unroll
-            for (int k = 0; k < 5; ++k) L[k] += (Fl[k] - Fh[k]) * g.inv_dx;
+            for (int k = 0; k < 5; ++k) L[k] += (s_f[k][lo] - s_f[k][hi]) * g.inv_dx;
+            const double pl0 = s_f[5][lo], pr0 = s_f[6][lo], ul0 = s_f[7][lo], ur0 = s_f[8][lo];
+            const double pl1 = s_f[5][hi], pr1 = s_f[6][hi], ul1 = s_f[7][hi], ur1 = s_f[8][hi];
             gradp[d] = (0.5 * (pl1 + pr1) - 0.5 * (pl0 + pr0)) * g.inv_dx;
             divpu += (0.5 * (pl1 * ul1 + pr1 * ur1) - 0.5 * (pl0 * ul0 + pr0 * ur0)) * g.inv_dx;
-        };
-        dir(std::integral_constant<int, 0>{});
-        dir(std::integral_constant<int, 1>{});
-        dir(std::integral_constant<int, 2>{});
-        double rho = A.P[c], E = A.qk[4 * N + c];
-        double a = A.aD[c], D = A.aD[N + c];
-        double ioma = 1.0 / (1.0 - a);
-        L[0] += rho * D * ioma;
-        for (int d = 0; d < 3; ++d) L[1 + d] += rho * A.P[(1 + d) * N + c] * D * ioma - a * gradp[d] * ioma;
-        L[4] += E * D * ioma - a * divpu * ioma;
-        for (int k = 0; k < 5; ++k) {
-            long long o = (long long)k * N + c;
-            if (A.rhs_mode) A.qo[o] = L[k];
-            else {
-                double r = A.b * (A.qk[o] + dt * L[k]);
-                if (A.a != 0.0) r += A.a * A.qn[o];
-                A.qo[o] = r;
-            }
+        }
+        __syncthreads();   // s_f is rewritten by the next direction
+    };
+    dir(std::integral_constant<int, 0>{});
+    dir(std::integral_constant<int, 1>{});
+    dir(std::integral_constant<int, 2>{});
+    if (!active) return;
+    double rho = A.P[c], E = A.qk[4 * N + c];
+    double a = A.aD[c], D = A.aD[N + c];
+    double ioma = 1.0 / (1.0 - a);
+    L[0] += rho * D * ioma;
+    for (int d = 0; d < 3; ++d) L[1 + d] += rho * A.P[(1 + d) * N + c] * D * ioma - a * gradp[d] * ioma;
+    L[4] += E * D * ioma - a * divpu * ioma;
+    for (int k = 0; k < 5; ++k) {
+        long long o = (long long)k * N + c;
+        if (A.rhs_mode) A.qo[o] = L[k];
+        else {
+            double r = A.b * (A.qk[o] + dt * L[k]);
+            if (A.a != 0.0) r += A.a * A.qn[o];
+            A.qo[o] = r;
         }
     }
 }
