@@ -58,6 +58,10 @@ def test_smear_and_gather(torch, bub, orc, bc):
     bub_h = orc.el_bubbles(pb, lc.bubbles[:3], lc.bubbles[3])
     bub_h[4] *= np.linspace(0.9, 1.3, lc.nbub)
     bub_h[5] = np.linspace(-2, 2, lc.nbub)
+    # large bubbles (kernel width h = R > dx): supports 11 and 19 cells wide, more (x, y) columns
+    # than a wavefront has lanes, and 67 cells wide, more z planes than lanes (wrapping around the
+    # periodic box several times, or mostly outside the reflective one)
+    bub_h[4, 2:5] = [1.5e-4, 2.9e-4, 11.0e-4]
     a_ref, d_ref = orc.el_smear(pb, bub_h)
     b_g = _gpu(torch, bub_h)
     aD = ctx.lagrangian_smear(b_g).cpu().numpy()
