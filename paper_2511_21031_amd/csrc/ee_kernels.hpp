@@ -48,9 +48,7 @@ __device__ __forceinline__ BinSums bin_sums(const double *__restrict__ q, const 
     const int nb = bins.nb, iNR = D + 3, iNV = D + 3 + nb;
     BinSums r;
     r.bad = nb;
-    for (int i = first; i < nb; i += stride) {
-        double x = q[(iNR + i) * N + c];
-        double y = q[(iNV + i) * N + c];
+    auto add = [&](int i, double x, double y) {
         if (!(x > 0.0) && r.bad == nb) r.bad = i;
         double wi = bins.w[i];
         double x2 = x * x, x3 = x2 * x;
@@ -59,7 +57,26 @@ __device__ __forceinline__ BinSums bin_sums(const double *__restrict__ q, const 
         r.s21 += wi * x2 * y;
         r.s32 += wi * x3 * y * y;
         r.sp += wi * bins.pg0[i] * x3 * exp2(ph.kappa3 * log2(bins.r0[i] * frcp(x)));
+    };
+    // The pass is bound by the latency of the bin loads: four bins' values are loaded together,
+    // then summed one bin at a time in bin order (scheduling barriers keep the loads grouped and
+    // the four sums apart, so registers stay few).
+    int i = first;
+    for (; i + 3 * stride < nb; i += 4 * stride) {
+        double x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            x[u] = q[(iNR + i + u * stride) * N + c];
+            y[u] = q[(iNV + i + u * stride) * N + c];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            __builtin_amdgcn_sched_barrier(0);
+            add(i + u * stride, x[u], y[u]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
+    for (; i < nb; i += stride) add(i, q[(iNR + i) * N + c], q[(iNV + i) * N + c]);
     return r;
 }
 
