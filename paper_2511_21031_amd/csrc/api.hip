@@ -36,7 +36,11 @@ long prof_begin(bub_ctx *c, int kind, hipStream_t s)
     if (!c->prof_on || c->prof_used >= PROF_MAX) return -1;
     if (c->prof_used == c->prof.size()) {
         ProfRec r;
-        if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return -1;
+        // timing only: no system-scope release at the end event, whose cache write-back would
+        // otherwise be counted into the kernel's time
+        if (hipEventCreateWithFlags(&r.a, hipEventDisableSystemFence) != hipSuccess ||
+            hipEventCreateWithFlags(&r.b, hipEventDisableSystemFence) != hipSuccess)
+            return -1;
         c->prof.push_back(r);
     }
     ProfRec &r = c->prof[c->prof_used];
@@ -878,8 +882,8 @@ int bub_autotune(bub_ctx *c, const double *q, double *scratch, int reps, double 
     A.rhs_mode = 1;
     A.sources = c->opts.bubble_mode == BUB_BUBBLES_UNSPLIT;
     hipEvent_t e0, e1;
-    HIP_OK(hipEventCreate(&e0));
-    HIP_OK(hipEventCreate(&e1));
+    HIP_OK(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+    HIP_OK(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
     const int keep = c->tile, prof = c->prof_on;
     c->prof_on = 0;
     double best_ms = 1e300;
