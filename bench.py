@@ -251,7 +251,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the hot path runs on a single MI355X and this build has no "
+        print("bench.py measures one GPU: the hot path runs on a single MI355X and the library has no "
               "multi-GPU path (run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
     if args.workload == "serving":

@@ -51,7 +51,7 @@ enum {
     BUB_ENONFINITE = -4,    /* device: NaN/Inf or inadmissible state (rho, alpha, p_l) */
     BUB_ENEGR = -5,         /* device: non-positive bubble radius */
     BUB_ESUBSTEP = -6,      /* device: adaptive bubble sub-step budget exhausted */
-    BUB_EUNSUPPORTED = -7   /* valid request this build does not support */
+    BUB_EUNSUPPORTED = -7   /* valid request the library does not support */
 };
 
 enum { BUB_BC_PERIODIC = 0, BUB_BC_REFLECTIVE = 1 };
