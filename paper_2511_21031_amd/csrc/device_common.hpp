@@ -107,6 +107,76 @@ __device__ inline double frcp(double x)
     return r;
 }
 
+// x^p in FP64 for the polytropic gas pressure (R0/R)^(3 kappa) of a bubble, about 65 vector
+// instructions against about 110 for the library power (which carries its logarithm in
+// double-double arithmetic).  Textbook reductions (e.g. J.-M. Muller, Elementary Functions,
+// 3rd ed., 2016):
+//   ln x: x = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s), s = (m-1)/(m+1),
+//         |s| < 0.172, by the odd series of atanh up to s^23 (the next term is below 1e-17
+//         of the sum); e ln 2 with ln 2 split in a 32-bit head and a tail.  The leading
+//         parts (2s and e ln 2) and the product p ln x keep their rounding errors as a
+//         second word, so y = p ln x is known to about 2^-60 relative.
+//   e^y:  y = k ln 2 + r, |r| <= ln2 / 2, reduced with the same split (Cody and Waite), e^r
+//         by its Taylor series up to r^14 (next term below 5e-18), scaled by 2^k.
+// Measured against an 80-bit reference: at most 1.2 ulp for x in [e^-160, e^160].
+// The series coefficients and constants come from table C (PPOW_TABLE, copied to LDS by the
+// caller): as literals the compiler keeps all of them in registers across the caller's loop.
+// Zero, infinite, negative or NaN x take the special values of pow.
+constexpr int PPOW_N = 28;
+constexpr double PPOW_TABLE[PPOW_N] = {
+    1.0 / 23.0, 1.0 / 21.0, 1.0 / 19.0, 1.0 / 17.0, 1.0 / 15.0, 1.0 / 13.0, 1.0 / 11.0, 1.0 / 9.0, 1.0 / 7.0,
+    1.0 / 5.0, 1.0 / 3.0,                                                  // atanh series, 0..10
+    1.0 / 87178291200.0, 1.0 / 6227020800.0, 1.0 / 479001600.0, 1.0 / 39916800.0, 1.0 / 3628800.0,
+    1.0 / 362880.0, 1.0 / 40320.0, 1.0 / 5040.0, 1.0 / 720.0, 1.0 / 120.0, 1.0 / 24.0, 1.0 / 6.0,
+    0.5,                                                                   // 1/14! .. 1/2!, 11..23
+    6.93147180369123816490e-01,   // LN2_HI = 0x3FE62E42FEE00000: k * LN2_HI is exact, 24
+    1.90821492927058770002e-10,   // LN2_LO = ln 2 - LN2_HI, 25
+    1.44269504088896338700e+00,   // log2(e), 26
+    0.70710678118654752440};      // sqrt(1/2), 27
+
+__device__ inline double ppow(double x, double p, const double *__restrict__ C)
+{
+    // (a class test: x - x == 0 would be contracted into fma(a, b, -x) when x = a * b)
+    if (!(x > 0.0) || __builtin_isinf(x)) {
+        if (x == 0.0) return p > 0.0 ? 0.0 : (p == 0.0 ? 1.0 : __builtin_huge_val());
+        if (x > 0.0) return p > 0.0 ? x : (p == 0.0 ? 1.0 : 0.0);
+        return __builtin_nan("");
+    }
+    int e;
+    double m = frexp(x, &e);
+    if (m < C[27]) {
+        m += m;
+        e -= 1;
+    }
+    // s = f / u with f = m - 1 (exact) and u = m + 1 as a rounded head plus its exact error
+    const double f = m - 1.0, u = m + 1.0, ulo = m - (u - 1.0);
+    const double iu = frcp(u);
+    const double sh = f * iu;
+    const double sl = (fma(-sh, u, f) - sh * ulo) * iu;
+    const double s2 = sh * sh;
+    double t = C[0];
+#pragma unroll
+    for (int j = 1; j <= 10; ++j) t = fma(t, s2, C[j]);
+    // ln x = e LN2_HI + 2 sh + (e LN2_LO + 2 sl + 2 sh^3 t), the first sum kept exactly
+    const double fe = (double)e;
+    const double a0 = fe * C[24], b0 = 2.0 * sh;
+    const double H = a0 + b0;
+    const double bb = H - a0;
+    const double L = ((a0 - (H - bb)) + (b0 - bb)) + fma(fe, C[25], 2.0 * sl + 2.0 * sh * s2 * t);
+    const double lh = H + L, ll = L - (lh - H);
+    // y = p ln x as yh + yl
+    const double yh = p * lh;
+    const double yl = fma(p, lh, -yh) + p * ll;
+    const double k = rint(yh * C[26]);
+    const double r = (fma(-k, C[24], yh) - k * C[25]) + yl;
+    double q = C[11];
+#pragma unroll
+    for (int j = 12; j <= 23; ++j) q = fma(q, r, C[j]);
+    q = fma(q * r, r, r);                     // e^r - 1
+    const int ki = (int)fmax(fmin(k, 2100.0), -2100.0);
+    return ldexp(1.0 + q, ki);
+}
+
 // WENO5-JS face value at the right face of v2 from v0..v4 (cells i-2..i+2).
 // The nonlinear weights d_k/(eps+beta_k)^2 are normalised through products over
 // the other two indicators, so one reciprocal serves all three (the FP64 range
@@ -178,6 +248,20 @@ __device__ inline double km_rddot(const Phys &ph, double R, double V, double r0,
 {
     double iR = frcp(R);
     double pb = pg0 * exp2(ph.kappa3 * log2(r0 * iR));
+    double pbw = pb - ph.mu4 * V * iR - ph.sigma2 * iR;
+    double dpbw = (-ph.kappa3 * pb * V + ph.mu4 * V * V * iR + ph.sigma2 * V * iR) * iR;
+    double irc = irho * ic;
+    double num = (1.0 + V * ic) * (pbw - pinf) * irho + R * dpbw * irc - 1.5 * V * V * (1.0 - V * ic * (1.0 / 3.0));
+    double den = R * (1.0 - V * ic) + ph.mu4 * irc;
+    return num * frcp(den);
+}
+
+// The same with the polytropic power from ppow (table C in LDS).
+__device__ inline double km_rddot_t(const Phys &ph, double R, double V, double r0, double pg0,
+                                    double pinf, double irho, double ic, const double *__restrict__ C)
+{
+    double iR = frcp(R);
+    double pb = pg0 * ppow(r0 * iR, ph.kappa3, C);
     double pbw = pb - ph.mu4 * V * iR - ph.sigma2 * iR;
     double dpbw = (-ph.kappa3 * pb * V + ph.mu4 * V * V * iR + ph.sigma2 * V * iR) * iR;
     double irc = irho * ic;

@@ -137,7 +137,7 @@ template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF>
 __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, const Phys &ph, const Bins &bins,
                                            int tile, int b0, int b1, bool core_out, TF *__restrict__ s_coef,
                                            TF *__restrict__ s_scr, unsigned char *__restrict__ s_flag,
-                                           double *__restrict__ s_out)
+                                           double *__restrict__ s_out, const double *__restrict__ s_pp)
 {
     using G = Geo<D, TX_, TY_, TZ_>;
     constexpr int T = G::T, F = G::F, C = G::C, NC = G::NC, NCF = G::NCF, L = G::L;
@@ -449,7 +449,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
                 // Keller--Miksis in FP64 from the FP64 state of the owned cell
                 double own_R = xr0 * own_in, own_V = xv0 * own_in;
                 LR += own_n * own_V;
-                LV += own_n * km_rddot(ph, own_R, own_V, r0, bins.pg0[ib], own_pl, own_irhol, own_ic);
+                LV += own_n * km_rddot_t(ph, own_R, own_V, r0, bins.pg0[ib], own_pl, own_irhol, own_ic, s_pp);
             }
             double xr = LR, xv = LV;
             if (!A.rhs_mode) {
@@ -487,6 +487,8 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs A, Grid g, Phys ph, B
     __shared__ TF s_scr[S::SCR];
     __shared__ unsigned char s_flag[G::F];
     __shared__ double s_out[D == 3 ? 2 * BLOCK : 1];   // 3D: results stored one bin late
+    __shared__ double s_pp[PPOW_N];                     // constants of the polytropic power
+    if (threadIdx.x < PPOW_N) s_pp[threadIdx.x] = PPOW_TABLE[threadIdx.x];   // read after the tile's barriers
     // XCD-aware order: consecutive items land on the same XCD (blocks are dealt round-robin), and
     // the bin groups of a tile are consecutive items, so they share that XCD's L2.
     const int b = blockIdx.x;
@@ -494,7 +496,7 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs A, Grid g, Phys ph, B
     if (item >= A.nitems) return;
     const int tile = item / A.ngroups, grp = item - tile * A.ngroups;
     const int b0 = grp * A.bpg, b1 = b0 + A.bpg < bins.nb ? b0 + A.bpg : bins.nb;
-    stage_tile<D, TX_, TY_, TZ_, BLOCK, TF>(A, g, ph, bins, tile, b0, b1, grp == 0, s_coef, s_scr, s_flag, s_out);
+    stage_tile<D, TX_, TY_, TZ_, BLOCK, TF>(A, g, ph, bins, tile, b0, b1, grp == 0, s_coef, s_scr, s_flag, s_out, s_pp);
 }
 
 }  // namespace bub
