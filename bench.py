@@ -111,7 +111,7 @@ def serving(args):
     torch.cuda.synchronize()
 
     budget = int(args.budget_gib * (1 << 30))
-    srv = Server(budget, max_slots=64, precision=bub.PREC_MIXED, bubble_mode=bub.BUBBLES_SPLIT, chunk=10,
+    srv = Server(budget, max_slots=args.slots, precision=bub.PREC_MIXED, bubble_mode=bub.BUBBLES_SPLIT, chunk=10,
                  lanes=args.lanes)
     ts = 0.0 if args.burst else 1.0
     recs = srv.run(reqs, workloads.request_case, time_scale=ts, progress=progress("served"))
@@ -135,7 +135,7 @@ def serving(args):
                                + ("all arriving at t=0" if args.burst else f"Poisson arrivals at {args.rate}/s")
                                + f" (70% 1D 200-4000 cells, 25% 2D 64^2-512^2, 5% 3D 96^3; 11/21/31 "
                                f"bins; 50-500 steps), split bubble sub-stepping, mixed precision",
-                   "hbm_budget_gib": args.budget_gib, "max_slots": 64, "chunk": 10, "lanes": args.lanes,
+                   "hbm_budget_gib": args.budget_gib, "max_slots": args.slots, "chunk": 10, "lanes": args.lanes,
                    "hw_queues": args.hw_queues or "HIP default",
                    "cell_bin_rk_steps": cell_bin_steps},
         "serving": {"p50_s": s_srv["p50_s"], "p99_s": s_srv["p99_s"], "mean_s": s_srv["mean_s"],
@@ -243,6 +243,7 @@ def main():
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--rate", type=float, default=20.0, help="serving: mean arrivals per second")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: HBM budget for resident solves")
+    ap.add_argument("--slots", type=int, default=64, help="serving: batch slots (resident problems at most)")
     ap.add_argument("--no-sequential", action="store_true", help="serving: skip the sequential FP64 baseline")
     ap.add_argument("--burst", action="store_true", help="serving: every request arrives at t = 0")
     ap.add_argument("--lanes", type=int, default=4, help="serving: batch streams")
