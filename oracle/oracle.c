@@ -13,22 +13,35 @@
  *   bins            Sec. 2.2 (log-normal PDF, Simpson's rule) -- pinned by
  *                   Simpson pattern/exactness and lognormal moments.
  *   primitives      Sec. 2 (mixture closures), eq. eos_liquid, eq. e:ndf,
- *                   eq. e:pressure -- pinned by equilibrium p = p0 and n recovery.
+ *                   eq. e:pressure -- pinned by equilibrium p = p0, n recovery
+ *                   and the low-frequency sound speed of the bubbly mixture
+ *                   (linear part of the bin moment of R^3 p_bw, the alpha
+ *                   source).  The R^3 Rdot^2 moment (quadratic in Rdot) is
+ *                   parity unpinned.
  *   Keller--Miksis  eq. keller_miksis with polytropic contents -- pinned by the
  *                   Rayleigh collapse time, the linearised oscillator and
- *                   equilibrium.
+ *                   equilibrium.  Its terms of second and higher order in
+ *                   Rdot/c are parity unpinned.
  *   WENO5           Sec. 3 (fifth-order WENO) -- pinned by quadratic exactness,
  *                   5th-order convergence, mirror symmetry.
  *   HLLC            Sec. 3 (HLLC Riemann solver) -- pinned by consistency,
- *                   contact at rest, the exact Sod solution.
+ *                   contact at rest, the exact Sod solution, passive fluxes
+ *                   = upwind specific value times mass flux, and a trace void
+ *                   fraction following the exact contact.
  *   semi-discrete   Sec. 3 eq. (finite-volume form) -- pinned by free-stream
  *                   preservation, discrete conservation, symmetry, 1D = 2D.
  *   SSP-RK3         Sec. 3 (third-order TVD RK) -- pinned by order >= 2.8 on the
  *                   0D uniform-state reduction.
  *   split sub-steps Sec. 3 (Strang splitting, RK3/RK2 pair, tolerance 1e-4)
- *                   -- pinned by the Rayleigh time and equilibrium.
+ *                   -- pinned by the Rayleigh time, equilibrium and the
+ *                   composition's observed order (2 at a trace void
+ *                   fraction; 1 where the void fraction feeds back on p_l,
+ *                   which the bin-by-bin sub-steps hold fixed).
  *   Lagrangian      Sec. 2.1 (kernel eq. kernel3D, smear, gather) -- pinned by
- *                   the kernel mass lattice sum, uniform gather, bubble at rest.
+ *                   the kernel mass lattice sum, uniform gather, bubble at rest;
+ *                   its liquid sources by exponential growth under a frozen
+ *                   uniform D and the wave speed c_l/sqrt(1-alpha) under a
+ *                   frozen uniform alpha.
  */
 #include "oracle.h"
 
