@@ -71,19 +71,46 @@ def measured_counters(precision: str, kernel: str):
     return None
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(case) -> dict:
+    """The FP64 oracle on this host: one RK3 step of the full grid on every thread, and one RK3 step of a
+    256 x 256 grid of the same recipe on one thread (a bounded sample; the full grid would take minutes)."""
     import oracle
+    import workloads
+    oracle.lib()
+    threads = oracle.num_threads()
     pb = oracle.problem_from_case(case)
     q = oracle.init_state(pb, case.prim)
     dt = oracle.cfl_dt(pb, q)
     t0 = time.perf_counter()
     oracle.rk3_step(pb, q, dt)
     t = time.perf_counter() - t0
+    small = workloads.c2(n=256, nb=case.nb)
+    pbs = oracle.problem_from_case(small)
+    qs = oracle.init_state(pbs, small.prim)
+    dts = oracle.cfl_dt(pbs, qs)
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.rk3_step(pbs, qs, dts)
+    t1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
     N = case.ncells
-    return {"value": 3 * N * case.nb / t, "unit": "cell·bin updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"one SSP-RK3 step (3 stages) of the full {case.n[0]}x{case.n[1]} grid with {case.nb} bins, "
-                      f"{t:.1f} s"}
+    return {"value": 3 * N * case.nb / t, "unit": "cell·bin updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"one SSP-RK3 step (3 stages) of the full {case.n[0]}x{case.n[1]} grid with {case.nb} bins "
+                      f"on {threads} threads, {t:.1f} s",
+            "cpu_model": cpu_model(),
+            "one_thread": {"value": 3 * small.ncells * small.nb / t1, "unit": "cell·bin updates/s", "cores": 1,
+                           "sample": f"one SSP-RK3 step of a {small.n[0]}x{small.n[1]} grid of the same recipe "
+                                     f"({small.nb} bins) on one thread, {t1:.1f} s"}}
 
 
 def serving(args):
@@ -237,6 +264,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed-run", action="store_true",
+                    help="stage workload: skip the run in the other precision on the same grid")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     ap.add_argument("--workload", choices=["stage", "serving", "collapse3d", "lagrangian"], default="stage")
@@ -272,7 +301,6 @@ def main():
     import torch
     import workloads
     import paper_2511_21031_amd as bub
-    from paper_2511_21031_amd._binding import K_STAGE, K_PRIM, K_OTHER
 
     torch.cuda.set_device(0)
     if args.calibrate_copy:
@@ -282,22 +310,81 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     case = workloads.c2()
-    prec = bub.PREC_FP64 if args.precision == "fp64" else bub.PREC_MIXED
+    N, nb = case.ncells, case.nb
+    first = args.precision
+    runs = {first: stage_run(bub, torch, case, first, args)}
+    if not args.no_mixed_run:
+        other = "mixed" if first == "fp64" else "fp64"
+        runs[other] = stage_run(bub, torch, case, other, args)
+    r = runs[first]
+    nvar = r["nvar"]
+    # algorithmic bytes of an RK stage: 16 nvar B/cell for stage 1 (read u^k, write u^(k+1)), 24 nvar
+    # for stages 2 and 3 (also read u^n); the fused stage kernel is the dominant kernel
+    bytes_per_launch = (16 + 24 + 24) / 3.0 * nvar * N
+    achieved = bytes_per_launch / (r["k_stage_avg_ms"] / 1e3) / 1e9
+    bytes_per_step = (16 + 24 + 24) * nvar * N
+    step_achieved = bytes_per_step / (r["ms_per_step"] / 1e3) / 1e9
+    rec = measured_counters(first, r["kname"])
+    traffic = rec["bytes_per_launch"] if rec else None
+    out = {
+        "metric": "cell·bin RK-stage updates/s",
+        "value": r["value"],
+        "unit": "cell·bin updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if first == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "2D 1024x1024 periodic ensemble-averaged, 31 log-normal bins (sigma 0.5), "
+                               "1 atm plane sine wave, CFL 0.3",
+                   "cells": N, "bins": nb, "nvar": nvar, "precision": first,
+                   "tile": r["tile"], "autotune_ms": r["autotune_ms"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        # every kernel of the step against the same algorithmic bytes (3 stages per step)
+        "step_roofline": {"bytes_per_step": bytes_per_step, "achieved": step_achieved, "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": step_achieved / HBM_PEAK_GBS},
+        # the second roofline: VALU issue (one wave64 FP64 instruction per CU per clock at full rate)
+        "valu": ({"wave_insts_per_launch": rec["valu_wave_insts_per_launch"],
+                  "achieved": rec["valu_wave_insts_per_launch"] / (r["k_stage_avg_ms"] / 1e3),
+                  "peak": VALU_PEAK_WAVE_INSTS, "unit": "wave-instructions/s",
+                  "frac": rec["valu_wave_insts_per_launch"] / (r["k_stage_avg_ms"] / 1e3) / VALU_PEAK_WAVE_INSTS}
+                 if rec else None),
+        "kernels": {k: r[k] for k in ("k_stage_avg_ms", "k_stage_launches", "k_prim_avg_ms", "k_prim_launches",
+                                      "other_avg_ms", "other_launches")},
+    }
+    for name, rr in runs.items():
+        if name == first:
+            continue
+        out[name] = {"value": rr["value"], "ms_per_step": rr["ms_per_step"], "k_stage_avg_ms": rr["k_stage_avg_ms"],
+                     "roofline_frac": bytes_per_launch / (rr["k_stage_avg_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS,
+                     "step_roofline_frac": bytes_per_step / (rr["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS,
+                     "tile": rr["tile"], "over_" + first: rr["value"] / r["value"]}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(out), flush=True)
+
+
+def stage_run(bub, torch, case, precision, args) -> dict:
+    """Autotune, warm up and time args.steps RK3 steps (one rk3_steps call) of `case` in one precision."""
+    from paper_2511_21031_amd._binding import K_STAGE, K_PRIM, K_OTHER
+    prec = bub.PREC_FP64 if precision == "fp64" else bub.PREC_MIXED
     ctx = bub.context_from_case(case, precision=prec)
     q = ctx.init_state(torch.from_numpy(case.prim).cuda())
     work = ctx.new_work()
     best, tile_ms = ctx.autotune(q, reps=5)     # project autotuner: fastest stage-kernel tile on this state
-    for _ in range(args.warmup):
-        ctx.rk3_step(q, work)
+    ctx.rk3_steps(q, work, args.warmup)
     torch.cuda.synchronize()
     for k in (K_STAGE, K_PRIM, K_OTHER):
         ctx.profile_read(k)
     ctx.profile(True)
-
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.rk3_step(q, work)
+    ctx.rk3_steps(q, work, args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.profile(False)
@@ -305,51 +392,23 @@ def main():
     if code != 0:
         print(f"device error {code} at cell {cell} bin {b}", file=sys.stderr)
         sys.exit(1)
-
     stage_ms, stage_n = ctx.profile_read(K_STAGE)
     prim_ms, prim_n = ctx.profile_read(K_PRIM)
+    other_ms, other_n = ctx.profile_read(K_OTHER)
     elapsed = t1 - t0
-    N, nb, nvar = case.ncells, case.nb, ctx.nvar
-    updates = N * nb * 3 * args.steps
-    value = updates / elapsed
-    avg_stage_s = stage_ms / 1e3 / max(stage_n, 1)
-    bytes_per_launch = (16 + 24 + 24) / 3.0 * nvar * N
-    achieved = bytes_per_launch / avg_stage_s / 1e9
     tx, ty, tz, blk = ctx.tiles()[best]
-    kname = f"void bub::k_stage<2, {tx}, {ty}, {tz}, {blk}, {'double' if args.precision == 'fp64' else 'float'}>"
-    rec = measured_counters(args.precision, kname)
-    traffic = rec["bytes_per_launch"] if rec else None
-    out = {
-        "metric": "cell·bin RK-stage updates/s",
-        "value": value,
-        "unit": "cell·bin updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
-        "data": "synthetic",
-        "config": {"workload": "2D 1024x1024 periodic ensemble-averaged, 31 log-normal bins (sigma 0.5), "
-                               "1 atm plane sine wave, CFL 0.3",
-                   "cells": N, "bins": nb, "nvar": nvar, "precision": args.precision,
-                   "tile": list(ctx.tiles()[best]), "autotune_ms": [round(m, 4) for m in tile_ms]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
-        # the second roofline: VALU issue (one wave64 FP64 instruction per CU per clock at full rate)
-        "valu": ({"wave_insts_per_launch": rec["valu_wave_insts_per_launch"],
-                  "achieved": rec["valu_wave_insts_per_launch"] / avg_stage_s,
-                  "peak": VALU_PEAK_WAVE_INSTS, "unit": "wave-instructions/s",
-                  "frac": rec["valu_wave_insts_per_launch"] / avg_stage_s / VALU_PEAK_WAVE_INSTS} if rec else None),
-        "kernels": {"k_stage_avg_ms": stage_ms / max(stage_n, 1), "k_stage_launches": stage_n,
-                    "k_prim_avg_ms": prim_ms / max(prim_n, 1), "k_prim_launches": prim_n,
-                    "stage_share_of_gpu_time": stage_ms / max(stage_ms + prim_ms, 1e-30)},
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case)
-    print(json.dumps(out), flush=True)
+    tf = "double" if precision == "fp64" else "float"
+    res = {"value": case.ncells * case.nb * 3 * args.steps / elapsed, "ms_per_step": elapsed / args.steps * 1e3,
+           "k_stage_avg_ms": stage_ms / max(stage_n, 1), "k_stage_launches": stage_n,
+           "k_prim_avg_ms": prim_ms / max(prim_n, 1), "k_prim_launches": prim_n,
+           "other_avg_ms": other_ms / max(other_n, 1), "other_launches": other_n,
+           "tile": [tx, ty, tz, blk], "autotune_ms": [round(m, 4) for m in tile_ms], "nvar": ctx.nvar,
+           "kname": f"void bub::k_stage<2, {tx}, {ty}, {tz}, {blk}, {tf}, true>"}
+    print(f"[stage] {precision}: {res['ms_per_step']:.3f} ms per step, stage kernel {res['k_stage_avg_ms']:.3f} ms, "
+          f"primitive pass {res['k_prim_avg_ms']:.3f} ms x {prim_n}", file=sys.stderr, flush=True)
+    del q, work, ctx
+    torch.cuda.empty_cache()
+    return res
 
 
 if __name__ == "__main__":

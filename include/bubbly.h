@@ -142,6 +142,14 @@ int bub_rhs_stage(bub_ctx *ctx, const double *q, double *rhs, void *stream);
  * S_b(dt/2) S_f(dt) S_b(dt/2) (Strang splitting, Sec. 3). */
 int bub_rk3_step(bub_ctx *ctx, double *q, double *work, double dt, double *dt_dev, void *stream);
 
+/* nsteps calls of bub_rk3_step in one (same arguments; dt_dev receives the last
+ * step's dt).  Results are bitwise those of nsteps separate calls.  In unsplit
+ * mode on grids of 2^19 cells or more, the last stage of each step but the
+ * final one also computes the primitives and wave speeds of the state it
+ * writes, so later steps start without a primitive pass of their own.
+ * BUB_EINVAL for nsteps < 0 or the argument errors of bub_rk3_step. */
+int bub_rk3_steps(bub_ctx *ctx, double *q, double *work, int nsteps, double dt, double *dt_dev, void *stream);
+
 /* Per-cell diagnostics out[8][N] (device): n, alpha, M3 = mean(R^3),
  * M2d = mean(R^2 Rdot), Mp = mean(R^3 p_bw), Mk = mean(R^3 Rdot^2), the mixture
  * pressure of eq. e:pressure and the liquid pressure p_l.  Means are the bin
@@ -159,6 +167,14 @@ int bub_moments(bub_ctx *ctx, const double *q, double *out, void *stream);
  * nsub (device int32 [nb][N], may be NULL) receives the accepted sub-step count
  * of every (cell, bin).  Valid in either bubble mode. */
 int bub_bubble_advance(bub_ctx *ctx, double *q, double tau, int32_t *nsub, void *stream);
+
+/* Sub-step counts of split-mode steps (diagnostics of the adaptive bubble
+ * sub-steps of Sec. 3).  While set, every bub_rk3_step of this context in split
+ * mode writes the accepted sub-step count of each (cell, bin) of its first and
+ * of its second bubble half-step into nsub[2][nb][N] (device int32, caller-owned,
+ * valid until the steps that use it have finished); NULL stops the recording.
+ * Results of the steps do not change. */
+int bub_substep_counts(bub_ctx *ctx, int32_t *nsub);
 
 /* ---- Volume-averaged (Euler--Lagrange) variant, Sec. 2.1 --------------------
  * Needs a 3D context with equal spacing in all directions; its bins are not

@@ -74,6 +74,8 @@ def lib():
         L.orc_km_integrate.restype = ctypes.c_int64
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
         L.orc_el_kernel.argtypes = [ctypes.c_double, ctypes.c_double]
         L.orc_el_kernel.restype = ctypes.c_double
         L.orc_el_smear.argtypes = [P, _dp, ctypes.c_int64, _dp, _dp]
@@ -136,6 +138,11 @@ def ncells(pb) -> int:
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads of later oracle calls (OpenMP)."""
+    lib().orc_set_threads(int(n))
 
 
 def bins(nb, r0_median, sigma_ln):

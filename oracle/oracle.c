@@ -831,3 +831,13 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the oracle's later parallel loops (for timing it on one core and on all). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -76,6 +76,9 @@ int orc_bubble_advance(const orc_problem *pb, double *q, double dt, int32_t *nsu
 /* OpenMP threads used by the parallel loops (1 without OpenMP). */
 int orc_num_threads(void);
 
+/* Threads of the oracle's later parallel loops (n > 0). */
+void orc_set_threads(int n);
+
 /* ---- scalar building blocks, exposed for the pins ---- */
 
 /* Keller--Miksis wall acceleration with polytropic contents (Sec. 2 eq. keller_miksis). */

@@ -65,6 +65,7 @@ _SIGS = {
     "bub_init_state": [_vp, _vp, _vp, _vp],
     "bub_rhs_stage": [_vp, _vp, _vp, _vp],
     "bub_rk3_step": [_vp, _vp, _vp, ctypes.c_double, _vp, _vp],
+    "bub_rk3_steps": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double, _vp, _vp],
     "bub_moments": [_vp, _vp, _vp, _vp],
     "bub_last_error": [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_int),
                        _vp],
@@ -82,6 +83,7 @@ _SIGS = {
     "bub_tile_set": [_vp, ctypes.c_int],
     "bub_tile_get": [_vp, ctypes.POINTER(ctypes.c_int)],
     "bub_bin_groups": [_vp, ctypes.c_int],
+    "bub_substep_counts": [_vp, _vp],
     "bub_autotune": [_vp, _vp, _vp, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int), _vp],
     "bub_batch_create": [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)],
     "bub_batch_destroy": [_vp],
@@ -240,6 +242,14 @@ class Context:
         _check(lib().bub_rk3_step(self._h, _ptr(q), _ptr(work), float(dt), _ptr(dt_dev), _stream(stream)),
                "bub_rk3_step")
 
+    def rk3_steps(self, q: torch.Tensor, work: torch.Tensor, nsteps: int, dt: float = 0.0,
+                  dt_dev: torch.Tensor | None = None, stream=None):
+        """nsteps RK3 steps in one call (bitwise nsteps calls of rk3_step)."""
+        if work.numel() * 8 < self.work_bytes:
+            raise ValueError("work buffer too small")
+        _check(lib().bub_rk3_steps(self._h, _ptr(q), _ptr(work), int(nsteps), float(dt), _ptr(dt_dev),
+                                   _stream(stream)), "bub_rk3_steps")
+
     def moments(self, q: torch.Tensor, out: torch.Tensor | None = None, stream=None):
         out = torch.empty((8, self.ncells), dtype=torch.float64, device=q.device) if out is None else out
         _check(lib().bub_moments(self._h, _ptr(q), _ptr(out), _stream(stream)), "bub_moments")
@@ -252,6 +262,16 @@ class Context:
         _check(lib().bub_bubble_advance(self._h, _ptr(q), float(tau),
                                         None if nsub is None else _vp(nsub.data_ptr()), _stream(stream)),
                "bub_bubble_advance")
+
+    def substep_counts(self, nsub: torch.Tensor | None):
+        """Record the sub-step counts of both bubble half-steps of later split-mode steps in nsub
+        (int32 [2][nb][N] on the GPU, kept alive by the caller), or stop recording (None)."""
+        if nsub is not None and (nsub.dtype != torch.int32 or not nsub.is_cuda or not nsub.is_contiguous()
+                                 or nsub.numel() != 2 * self.nb * self.ncells):
+            raise ValueError("nsub must be a contiguous int32 GPU tensor of 2*nb*N entries")
+        self._nsub = nsub
+        _check(lib().bub_substep_counts(self._h, None if nsub is None else _vp(nsub.data_ptr())),
+               "bub_substep_counts")
 
     # -- volume-averaged (Euler--Lagrange) variant ------------------------------
     def lagrangian_work(self, nbub: int, device="cuda"):

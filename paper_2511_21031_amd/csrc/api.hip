@@ -143,6 +143,25 @@ int launch_prim(bub_ctx *c, const double *q, double *out, int mode, hipStream_t 
     return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
 }
 
+// Bin groups: small grids give each tile several workgroups (a range of bins each) so the launch
+// still fills the chip; large grids keep one workgroup per tile (no repeated mixture faces).
+// Returns the bins per group; *groups receives the workgroups per tile.
+int bin_grouping(const bub_ctx *c, long long ntiles, int *groups)
+{
+    int ng = c->bin_groups;
+    if (ng <= 0) {
+        constexpr int target = 1024;   // work items that keep 256 CUs busy
+        ng = ntiles >= target ? 1 : (int)((target + ntiles - 1) / ntiles);
+        const int cap = (c->nb + 1) / 2;  // at least two bins per group
+        if (ng > cap) ng = cap;
+    }
+    if (ng < 1) ng = 1;
+    if (ng > c->nb) ng = c->nb;
+    const int bpg = (c->nb + ng - 1) / ng;
+    *groups = (c->nb + bpg - 1) / bpg;
+    return bpg;
+}
+
 template <int D, int V, typename TF>
 int launch_stage_t(bub_ctx *c, StageArgs A, hipStream_t s)
 {
@@ -152,24 +171,17 @@ int launch_stage_t(bub_ctx *c, StageArgs A, hipStream_t s)
     A.ntile[1] = (c->g.n[1] + G::TY - 1) / G::TY;
     A.ntile[2] = (c->g.n[2] + G::TZ - 1) / G::TZ;
     A.ntiles = A.ntile[0] * A.ntile[1] * A.ntile[2];
-    // bin groups: small grids give each tile several workgroups (a range of bins each) so the launch
-    // still fills the chip; large grids keep one workgroup per tile (no repeated mixture faces)
-    int ng = c->bin_groups;
-    if (ng <= 0) {
-        constexpr int target = 1024;   // work items that keep 256 CUs busy
-        ng = A.ntiles >= target ? 1 : (target + A.ntiles - 1) / A.ntiles;
-        const int cap = (c->nb + 1) / 2;  // at least two bins per group
-        if (ng > cap) ng = cap;
-    }
-    if (ng < 1) ng = 1;
-    if (ng > c->nb) ng = c->nb;
-    A.bpg = (c->nb + ng - 1) / ng;
-    A.ngroups = (c->nb + A.bpg - 1) / A.bpg;
+    A.bpg = bin_grouping(c, A.ntiles, &A.ngroups);
+    if (A.Pout && A.ngroups != 1) return BUB_EINVAL;   // the fused epilogue needs every bin of a cell
     A.nitems = A.ntiles * A.ngroups;
     A.nblk_per_xcd = (A.nitems + 7) / 8;
     long pr = prof_begin(c, BUB_K_STAGE, s);
-    hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF>), dim3(8 * A.nblk_per_xcd),
-                       dim3(TC::BLOCK), 0, s, A, c->g, c->ph, c->bt);
+    if (A.Pout)
+        hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF, true>), dim3(8 * A.nblk_per_xcd),
+                           dim3(TC::BLOCK), 0, s, A, c->g, c->ph, c->bt);
+    else
+        hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF, false>), dim3(8 * A.nblk_per_xcd),
+                           dim3(TC::BLOCK), 0, s, A, c->g, c->ph, c->bt);
     prof_end(c, pr, s);
     return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
 }
@@ -253,6 +265,25 @@ int stage(bub_ctx *c, const StageArgs &A, hipStream_t s)
     }
 }
 
+// Tiles of the context's current stage shape.
+long long stage_tiles(const bub_ctx *c)
+{
+    int tx, ty, tz, blk;
+    bub_tile_info(c, c->tile, &tx, &ty, &tz, &blk);
+    return (long long)((c->g.n[0] + tx - 1) / tx) * ((c->g.n[1] + ty - 1) / ty) * ((c->g.n[2] + tz - 1) / tz);
+}
+
+// The stage kernels can carry the primitive pass of the state they write (fused epilogue) when one
+// workgroup owns all bins of a tile and the grid is large enough that the primitive pass would take
+// one thread per cell (then both forms sum the bins in the same order, so results are bitwise equal).
+bool stage_fusable(const bub_ctx *c)
+{
+    if (!c->d_P2 || slots_for(c->N) != 1) return false;
+    int groups = 0;
+    bin_grouping(c, stage_tiles(c), &groups);
+    return groups == 1;
+}
+
 }  // namespace
 
 extern "C" {
@@ -305,12 +336,16 @@ __global__ void k_err_copy(const Scalars *sc, int64_t *dst)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Device-buffer layout of a context: bin table | scalars | primitive scratch.
-void ctx_buffer_layout(int ndim, long long N, size_t *off_sc, size_t *off_P, size_t *total)
+// Device-buffer layout of a context: bin table | scalars | primitive scratch | second primitive
+// scratch (only for grids of 2^19 cells or more, whose stages carry the primitive pass; off_P2 = 0
+// otherwise).
+void ctx_buffer_layout(int ndim, long long N, size_t *off_sc, size_t *off_P, size_t *off_P2, size_t *total)
 {
+    const size_t pbytes = align256(sizeof(double) * (size_t)(ndim + 6) * (size_t)N);
     *off_sc = align256(sizeof(double) * 3 * NB_MAX);
     *off_P = *off_sc + align256(sizeof(Scalars));
-    *total = *off_P + align256(sizeof(double) * (size_t)(ndim + 6) * (size_t)N);
+    *off_P2 = slots_for(N) == 1 ? *off_P + pbytes : 0;
+    *total = *off_P + pbytes + (*off_P2 ? pbytes : 0);
 }
 
 void ctx_finish(bub_ctx *c)
@@ -327,12 +362,11 @@ void bin_table(const bub_ctx *c, double *tab)
     std::memcpy(tab + 2 * c->nb, c->h_pg0, sizeof(double) * c->nb);
 }
 
-// Validate the inputs and build the host side of a context (no device memory yet).
-int ctx_setup(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, const bub_bins *bins,
-              const bub_opts *opts, bub_ctx **out)
+// Validate the inputs and fill the host side of a context held by the caller (no allocation).
+int ctx_fill(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, const bub_bins *bins,
+             const bub_opts *opts, bub_ctx *c)
 {
-    if (!grid || !liq || !gas || !bins || !opts || !out) return BUB_EINVAL;
-    *out = nullptr;
+    if (!grid || !liq || !gas || !bins || !opts || !c) return BUB_EINVAL;
     if (grid->ndim < 1 || grid->ndim > 3) return BUB_EINVAL;
     long long N = 1;
     for (int d = 0; d < 3; ++d) {
@@ -355,18 +389,13 @@ int ctx_setup(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, c
     if (opts->bubble_mode == BUB_BUBBLES_SPLIT && (!(opts->sub_rtol > 0.0) || opts->max_substeps < 1))
         return BUB_EINVAL;
 
-    bub_ctx *c = new (std::nothrow) bub_ctx();
-    if (!c) return BUB_ENOMEM;
     c->grid = *grid;
     c->liq = *liq;
     c->gas = *gas;
     c->bins = *bins;
     c->opts = *opts;
     int rc = make_bins(bins->nb, bins->r0_median, bins->sigma_ln, c->h_r0, c->h_w);
-    if (rc) {
-        delete c;
-        return rc;
-    }
+    if (rc) return rc;
     c->ndim = grid->ndim;
     c->nb = bins->nb;
     c->nvar = c->ndim + 3 + 2 * c->nb;
@@ -377,10 +406,7 @@ int ctx_setup(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, c
         c->h_pg0[i] = liq->p0 + 2.0 * gas->sigma / c->h_r0[i] - gas->pv;
         m3 += c->h_w[i] * c->h_r0[i] * c->h_r0[i] * c->h_r0[i];
     }
-    if (hipGetDevice(&c->device) != hipSuccess) {
-        delete c;
-        return BUB_EHIP;
-    }
+    if (hipGetDevice(&c->device) != hipSuccess) return BUB_EHIP;
     c->ph.gamma = liq->gamma;
     c->ph.pi_inf = liq->pi_inf;
     c->ph.gm1 = liq->gamma - 1.0;
@@ -402,6 +428,22 @@ int ctx_setup(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, c
     c->bt.pg0 = c->d_bins + 2 * c->nb;
     c->bt.nb = c->nb;
     c->bt.m3_eq = m3;
+    return BUB_OK;
+}
+
+// Validate the inputs and build the host side of a heap context (no device memory yet).
+int ctx_setup(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, const bub_bins *bins,
+              const bub_opts *opts, bub_ctx **out)
+{
+    if (!out) return BUB_EINVAL;
+    *out = nullptr;
+    bub_ctx *c = new (std::nothrow) bub_ctx();
+    if (!c) return BUB_ENOMEM;
+    const int rc = ctx_fill(grid, liq, gas, bins, opts, c);
+    if (rc) {
+        delete c;
+        return rc;
+    }
     *out = c;
     return BUB_OK;
 }
@@ -419,7 +461,8 @@ int bub_ctx_create(const bub_grid *grid, const bub_liquid *liq, const bub_gas *g
     size_t pbytes = sizeof(double) * (size_t)c->nprim * (size_t)c->N;
     c->owns = true;
     if (hipMalloc(&c->d_bins, sizeof(double) * 3 * NB_MAX) != hipSuccess ||
-        hipMalloc(&c->d_P, pbytes) != hipSuccess || hipMalloc(&c->d_sc, sizeof(Scalars)) != hipSuccess) {
+        hipMalloc(&c->d_P, pbytes) != hipSuccess || hipMalloc(&c->d_sc, sizeof(Scalars)) != hipSuccess ||
+        (slots_for(c->N) == 1 && hipMalloc(&c->d_P2, pbytes) != hipSuccess)) {
         bub_ctx_destroy(c);
         return BUB_ENOMEM;
     }
@@ -444,8 +487,8 @@ int bub_ctx_buffer_bytes(const bub_grid *grid, const bub_bins *bins, size_t *byt
         if (grid->n[d] < 1) return BUB_EINVAL;
         N *= grid->n[d];
     }
-    size_t a, b;
-    ctx_buffer_layout(grid->ndim, N, &a, &b, bytes);
+    size_t a, b, p2;
+    ctx_buffer_layout(grid->ndim, N, &a, &b, &p2, bytes);
     return BUB_OK;
 }
 
@@ -456,8 +499,8 @@ int bub_ctx_create_on(const bub_grid *grid, const bub_liquid *liq, const bub_gas
     bub_ctx *c = nullptr;
     int rc = ctx_setup(grid, liq, gas, bins, opts, &c);
     if (rc) return rc;
-    size_t off_sc, off_P, total;
-    ctx_buffer_layout(c->ndim, c->N, &off_sc, &off_P, &total);
+    size_t off_sc, off_P, off_P2, total;
+    ctx_buffer_layout(c->ndim, c->N, &off_sc, &off_P, &off_P2, &total);
     if (bytes < total) {
         delete c;
         return BUB_EINVAL;
@@ -467,6 +510,7 @@ int bub_ctx_create_on(const bub_grid *grid, const bub_liquid *liq, const bub_gas
     c->d_bins = (double *)base;
     c->d_sc = (Scalars *)(base + off_sc);
     c->d_P = (double *)(base + off_P);
+    c->d_P2 = off_P2 ? (double *)(base + off_P2) : nullptr;
     BinTable t{};
     bin_table(c, t.v);
     hipLaunchKernelGGL(k_ctx_init, dim3(1), dim3(64), 0, (hipStream_t)stream, c->d_bins, t, 3 * c->nb, c->d_sc);
@@ -486,6 +530,7 @@ int bub_ctx_destroy(bub_ctx *c)
         (void)hipDeviceSynchronize();
         if (c->d_bins) (void)hipFree(c->d_bins);
         if (c->d_P) (void)hipFree(c->d_P);
+        if (c->d_P2) (void)hipFree(c->d_P2);
         if (c->d_sc) (void)hipFree(c->d_sc);
     }
     for (ProfRec &r : c->prof) {
@@ -535,10 +580,12 @@ int bub_moments(bub_ctx *c, const double *q, double *out, void *stream)
     return prim(c, q, out, PRIM_MOMENTS, (hipStream_t)stream);
 }
 
-int bub_rhs_stage(bub_ctx *c, const double *q, double *rhs, void *stream)
+}  // extern "C"
+
+namespace {
+
+int rhs_stage_impl(bub_ctx *c, const double *q, double *rhs, hipStream_t s)
 {
-    if (!c || !q || !rhs || q == rhs) return BUB_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
     int rc = prim(c, q, c->d_P, PRIM_ONLY, s);
     if (rc) return rc;
     StageArgs A{};
@@ -554,45 +601,104 @@ int bub_rhs_stage(bub_ctx *c, const double *q, double *rhs, void *stream)
     return stage(c, A, s);
 }
 
-int bub_rk3_step(bub_ctx *c, double *q, double *work, double dt, double *dt_dev, void *stream)
+}  // namespace
+
+extern "C" {
+
+int bub_rhs_stage(bub_ctx *c, const double *q, double *rhs, void *stream)
 {
-    if (!c || !q || !work) return BUB_EINVAL;
-    if (!(dt == dt) || dt == INFINITY) return BUB_EINVAL;
+    if (!c || !q || !rhs || q == rhs) return BUB_EINVAL;
+    return rhs_stage_impl(c, q, rhs, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// nsteps SSP-RK3 steps (Sec. 3).  With the fused epilogue (stage_fusable), stages 1 and 2 write the
+// primitives of the state they produce (P -> P2 -> P), so only the step's first stage needs a
+// primitive pass; in unsplit mode stage 3 of every step but the last also writes the primitives and
+// the wave-speed maxima of u^{n+1}, so the next step needs none.  Results are bitwise those of the
+// unfused sequence (same arithmetic, same bin order).
+int rk3_steps_impl(bub_ctx *c, double *q, double *work, int nsteps, double dt, double *dt_dev, hipStream_t s)
+{
     const bool split = c->opts.bubble_mode == BUB_BUBBLES_SPLIT;
     const size_t M = (size_t)c->nvar * (size_t)c->N;
     double *w1 = work, *w2 = work + M;
-    if ((q >= work && q < work + 2 * M) || (work >= q && work < q + M)) return BUB_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
     const bool cfl = !(dt > 0.0);
-    int rc = prim(c, q, c->d_P, cfl ? PRIM_CFL : PRIM_ONLY, s);
-    if (rc) return rc;
-    long pr = prof_begin(c, BUB_K_OTHER, s);
-    hipLaunchKernelGGL(k_dt, dim3(1), dim3(WMAX_SLOTS), 0, s, c->d_sc, cfl ? 0.0 : dt, c->opts.cfl, dt_dev);
-    prof_end(c, pr, s);
-    HIP_OK(hipGetLastError());
-    if (split) {
-        // S_b(dt/2) first; the flux part then starts from the primitives of the advanced state
-        if ((rc = bubble(c, q, &c->d_sc->dt, 0.5, 0.0, nullptr, s))) return rc;
-        if ((rc = prim(c, q, c->d_P, PRIM_ONLY, s))) return rc;
+    const bool fuse = stage_fusable(c);
+    const bool carry = fuse && !split;   // the last bubble half-step of split mode changes u^{n+1}
+    double *Pa = c->d_P, *Pb = c->d_P2;  // Pa: primitives of the step's starting state
+    int rc = BUB_OK;
+    for (int k = 0; k < nsteps; ++k) {
+        const bool more = k + 1 < nsteps;
+        if ((k == 0 || !carry) && (rc = prim(c, q, Pa, cfl ? PRIM_CFL : PRIM_ONLY, s))) return rc;
+        long pr = prof_begin(c, BUB_K_OTHER, s);
+        hipLaunchKernelGGL(k_dt, dim3(1), dim3(WMAX_SLOTS), 0, s, c->d_sc, cfl ? 0.0 : dt, c->opts.cfl, dt_dev);
+        prof_end(c, pr, s);
+        HIP_OK(hipGetLastError());
+        if (split) {
+            // S_b(dt/2) first; the flux part then starts from the primitives of the advanced state
+            if ((rc = bubble(c, q, &c->d_sc->dt, 0.5, 0.0, c->nsub_diag, s))) return rc;
+            if ((rc = prim(c, q, Pa, PRIM_ONLY, s))) return rc;
+        }
+        StageArgs A{};
+        A.dtp = &c->d_sc->dt;
+        A.rhs_mode = 0;
+        A.sources = split ? 0 : 1;
+        A.sc = c->d_sc;
+        // stage 1: u1 = u^n + dt L(u^n)
+        A.qk = q; A.qn = nullptr; A.qo = w1; A.a = 0.0; A.b = 1.0;
+        A.P = Pa;
+        A.Pout = fuse ? Pb : nullptr;
+        if ((rc = stage(c, A, s))) return rc;
+        // stage 2: u2 = 3/4 u^n + 1/4 (u1 + dt L(u1))
+        if (!fuse && (rc = prim(c, w1, Pa, PRIM_ONLY, s))) return rc;
+        A.qk = w1; A.qn = q; A.qo = w2; A.a = 0.75; A.b = 0.25;
+        A.P = fuse ? Pb : Pa;
+        A.Pout = fuse ? Pa : nullptr;
+        if ((rc = stage(c, A, s))) return rc;
+        // stage 3: u^{n+1} = 1/3 u^n + 2/3 (u2 + dt L(u2)), written over u^n (own-cell reads only)
+        if (!fuse && (rc = prim(c, w2, Pa, PRIM_ONLY, s))) return rc;
+        A.qk = w2; A.qn = q; A.qo = q; A.a = 1.0 / 3.0; A.b = 2.0 / 3.0;
+        A.P = Pa;
+        A.Pout = carry && more ? Pb : nullptr;
+        A.cfl = carry && more && cfl;
+        if ((rc = stage(c, A, s))) return rc;
+        if (split &&   // S_b(dt/2)
+            (rc = bubble(c, q, &c->d_sc->dt, 0.5, 0.0,
+                         c->nsub_diag ? c->nsub_diag + (size_t)c->nb * c->N : nullptr, s)))
+            return rc;
+        if (carry && more) std::swap(Pa, Pb);
     }
-    StageArgs A{};
-    A.P = c->d_P;
-    A.dtp = &c->d_sc->dt;
-    A.rhs_mode = 0;
-    A.sources = split ? 0 : 1;
-    // stage 1: u1 = u^n + dt L(u^n)
-    A.qk = q; A.qn = nullptr; A.qo = w1; A.a = 0.0; A.b = 1.0;
-    if ((rc = stage(c, A, s))) return rc;
-    // stage 2: u2 = 3/4 u^n + 1/4 (u1 + dt L(u1))
-    if ((rc = prim(c, w1, c->d_P, PRIM_ONLY, s))) return rc;
-    A.qk = w1; A.qn = q; A.qo = w2; A.a = 0.75; A.b = 0.25;
-    if ((rc = stage(c, A, s))) return rc;
-    // stage 3: u^{n+1} = 1/3 u^n + 2/3 (u2 + dt L(u2)), written over u^n (own-cell reads only)
-    if ((rc = prim(c, w2, c->d_P, PRIM_ONLY, s))) return rc;
-    A.qk = w2; A.qn = q; A.qo = q; A.a = 1.0 / 3.0; A.b = 2.0 / 3.0;
-    if ((rc = stage(c, A, s))) return rc;
-    if (split) rc = bubble(c, q, &c->d_sc->dt, 0.5, 0.0, nullptr, s);   // S_b(dt/2)
     return rc;
+}
+
+int rk3_check(const bub_ctx *c, const double *q, const double *work, double dt)
+{
+    if (!c || !q || !work) return BUB_EINVAL;
+    if (!(dt == dt) || dt == INFINITY) return BUB_EINVAL;
+    const size_t M = (size_t)c->nvar * (size_t)c->N;
+    if ((q >= work && q < work + 2 * M) || (work >= q && work < q + M)) return BUB_EINVAL;
+    return BUB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bub_rk3_step(bub_ctx *c, double *q, double *work, double dt, double *dt_dev, void *stream)
+{
+    int rc = rk3_check(c, q, work, dt);
+    return rc ? rc : rk3_steps_impl(c, q, work, 1, dt, dt_dev, (hipStream_t)stream);
+}
+
+int bub_rk3_steps(bub_ctx *c, double *q, double *work, int nsteps, double dt, double *dt_dev, void *stream)
+{
+    int rc = rk3_check(c, q, work, dt);
+    if (rc) return rc;
+    if (nsteps < 0) return BUB_EINVAL;
+    return rk3_steps_impl(c, q, work, nsteps, dt, dt_dev, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -815,6 +921,13 @@ int bub_error_copy(const bub_ctx *c, int64_t *dst, void *stream)
     if (!c || !dst) return BUB_EINVAL;
     hipLaunchKernelGGL(k_err_copy, dim3(1), dim3(64), 0, (hipStream_t)stream, c->d_sc, dst);
     HIP_OK(hipGetLastError());
+    return BUB_OK;
+}
+
+int bub_substep_counts(bub_ctx *c, int32_t *nsub)
+{
+    if (!c) return BUB_EINVAL;
+    c->nsub_diag = nsub;
     return BUB_OK;
 }
 
@@ -1204,3 +1317,4 @@ int bub_batch_autotune(bub_batch *b, int reps, int *classes, void *stream)
 }
 
 }  // extern "C"
+

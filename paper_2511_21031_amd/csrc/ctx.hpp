@@ -25,6 +25,7 @@ struct bub_ctx {
     double h_r0[bub::NB_MAX]{}, h_w[bub::NB_MAX]{}, h_pg0[bub::NB_MAX]{};
     double *d_bins = nullptr;    // [3][nb]: r0, w, pg0
     double *d_P = nullptr;       // [nprim][N] primitive scratch
+    double *d_P2 = nullptr;      // second primitive scratch of the fused stages (grids of 2^19 cells or more)
     bub::Scalars *d_sc = nullptr;
     bub::Phys ph{};
     bub::Grid g{};
@@ -32,6 +33,7 @@ struct bub_ctx {
     bool owns = true;            // device buffers allocated (and freed) by the library
     int tile = 0;                // stage-kernel tile shape (index into the per-dimension list)
     int bin_groups = 0;          // stage-kernel workgroups per tile (0: chosen per launch from the tile count)
+    int32_t *nsub_diag = nullptr;   // split-mode steps record their sub-step counts here ([2][nb][N])
     int prof_on = 0;
     size_t prof_used = 0;
     std::vector<ProfRec> prof;

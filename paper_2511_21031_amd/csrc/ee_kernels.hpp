@@ -31,33 +31,41 @@ enum PrimMode { PRIM_ONLY = 0, PRIM_CFL = 1, PRIM_MOMENTS = 2 };
 
 constexpr int PRIM_SLOTS = 8;   // threads per cell in the primitive pass
 
-// Bin sums of the primitive pass over bins i = first, first + stride, ... in the
-// conserved variables x = nR, y = nRdot.  With R = x/n and Rdot = y/n every moment
-// is a power of n times a sum that does not involve n, including the contents term
+// Bin sums of the primitive pass in the conserved variables x = nR, y = nRdot.  With R = x/n and
+// Rdot = y/n every moment is a power of n times a sum that does not involve n, including the
+// contents term
 //   R^3 p_b(R) = p_g0 R^3 (R0/R)^(3 kappa) = n^(3 kappa - 3) p_g0 x^3 (R0/x)^(3 kappa).
-// bad = the first bin of the subset with x <= 0 (n > 0, so R_i has the sign of x), or nb.
+// bad = the first bin with x <= 0 (n > 0, so R_i has the sign of x), or nb.
 struct BinSums {
     double s3 = 0.0, s2 = 0.0, s21 = 0.0, s32 = 0.0, sp = 0.0;
     int bad;
 };
 
+// One bin's terms added to the sums.  Shared by the primitive pass and the epilogue of the fused
+// stage kernel, with its operation order fixed (explicit fused multiply-adds, no contraction), so both
+// give bitwise the same primitives.  C: the power's constant table (PPOW_TABLE, in LDS).
+__device__ __forceinline__ void bin_add(BinSums &r, int i, double x, double y, double w, double pg0, double r0,
+                                        int nb, const Phys &ph, const double *__restrict__ C)
+{
+#pragma clang fp contract(off)
+    if (!(x > 0.0) && r.bad == nb) r.bad = i;
+    const double x2 = x * x, x3 = x2 * x;
+    const double wx2 = w * x2, wx3 = w * x3;
+    r.s3 = fma(w, x3, r.s3);
+    r.s2 = fma(w, x2, r.s2);
+    r.s21 = fma(wx2, y, r.s21);
+    r.s32 = fma(wx3 * y, y, r.s32);
+    r.sp = fma(wx3 * pg0, ppow(r0 * frcp(x), ph.kappa3, C), r.sp);
+}
+
 template <int D>
 __device__ __forceinline__ BinSums bin_sums(const double *__restrict__ q, const Phys &ph, const Bins &bins,
-                                            long long N, long long c, int first, int stride)
+                                            long long N, long long c, int first, int stride,
+                                            const double *__restrict__ C)
 {
     const int nb = bins.nb, iNR = D + 3, iNV = D + 3 + nb;
     BinSums r;
     r.bad = nb;
-    auto add = [&](int i, double x, double y) {
-        if (!(x > 0.0) && r.bad == nb) r.bad = i;
-        double wi = bins.w[i];
-        double x2 = x * x, x3 = x2 * x;
-        r.s3 += wi * x3;
-        r.s2 += wi * x2;
-        r.s21 += wi * x2 * y;
-        r.s32 += wi * x3 * y * y;
-        r.sp += wi * bins.pg0[i] * x3 * exp2(ph.kappa3 * log2(bins.r0[i] * frcp(x)));
-    };
     // The pass is bound by the latency of the bin loads: four bins' values are loaded together,
     // then summed one bin at a time in bin order (scheduling barriers keep the loads grouped and
     // the four sums apart, so registers stay few).
@@ -72,12 +80,75 @@ __device__ __forceinline__ BinSums bin_sums(const double *__restrict__ q, const 
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             __builtin_amdgcn_sched_barrier(0);
-            add(i + u * stride, x[u], y[u]);
+            const int k = i + u * stride;
+            bin_add(r, k, x[u], y[u], bins.w[k], bins.pg0[k], bins.r0[k], nb, ph, C);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
-    for (; i < nb; i += stride) add(i, q[(iNR + i) * N + c], q[(iNV + i) * N + c]);
+    for (; i < nb; i += stride)
+        bin_add(r, i, q[(iNR + i) * N + c], q[(iNV + i) * N + c], bins.w[i], bins.pg0[i], bins.r0[i], nb, ph, C);
     return r;
+}
+
+// Mixture primitives of one cell from its conserved mixture variables (rho, rho u, E, alpha):
+// u, p_l (eq. eos_liquid through the mixture energy), the liquid sound speed, and whether the
+// state is admissible.  Shared by the primitive pass and the fused stage epilogue.
+template <int D>
+struct CellCore {
+    double u[3], pl, cs;
+    bool bad;
+};
+
+template <int D>
+__device__ __forceinline__ CellCore<D> cell_core(double rho, const double *mom, double E, double a, const Phys &ph)
+{
+#pragma clang fp contract(off)
+    CellCore<D> o;
+    double ke = 0.0;
+    const double irho = frcp(rho);
+    o.u[0] = o.u[1] = o.u[2] = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        o.u[d] = mom[d] * irho;
+        ke = fma(o.u[d], o.u[d], ke);
+    }
+    ke *= 0.5 * rho;
+    const double oma = 1.0 - a;
+    o.pl = ph.gm1 * (E - ke) / oma - ph.gpi;
+    const double rhol = rho / oma;
+    o.cs = sqrt(ph.gamma * (o.pl + ph.pi_inf) / rhol);
+    o.bad = !(rho > 0.0) || !(a >= 0.0 && a < 1.0) || !(o.pl + ph.pi_inf > 0.0) || !(o.cs < 1e300);
+    return o;
+}
+
+// Bin moments, n, B = (Mp - rho Mk)/M3 (eq. e:pressure) and the alpha source 3 alpha M2d/M3
+// (eq. e:alpha) of one cell from its bin sums (eq. e:ndf gives n).
+struct CellBins {
+    double n, B, Sa, M3, M2d, Mp, Mk;
+};
+
+__device__ __forceinline__ CellBins cell_bins(double rho, double a, const BinSums &t, const Phys &ph, const Bins &bins)
+{
+#pragma clang fp contract(off)
+    CellBins o{};
+    if (a > 0.0) {
+        o.n = sqrt(FOUR_PI_3 * t.s3 / a);
+        const double in = frcp(o.n);
+        const double in2 = in * in, in3 = in2 * in;
+        o.M3 = t.s3 * in3;
+        o.M2d = t.s21 * in3;
+        o.Mk = t.s32 * in3 * in2;
+        o.Mp = exp2((ph.kappa3 - 3.0) * log2(o.n)) * t.sp - ph.mu4 * o.M2d - ph.sigma2 * t.s2 * in2;
+        const double iM3 = frcp(o.M3);
+        o.B = (o.Mp - rho * o.Mk) * iM3;
+        o.Sa = 3.0 * a * o.M2d * iM3;
+    } else {
+        for (int i = 0; i < bins.nb; ++i) {
+            const double r = bins.r0[i];
+            o.M3 += bins.w[i] * r * r * r;
+        }
+    }
+    return o;
 }
 
 // The rest of one cell of the primitive pass, given its bin sums: primitives, moments,
@@ -89,69 +160,40 @@ __device__ __forceinline__ double prim_finish(const double *__restrict__ q, doub
 {
     const long long N = g.N;
     const int nb = bins.nb;
-    const int iE = D + 1, iA = D + 2;
-    double wmax = 0.0;
-    double rho = q[c];
-    double u[3] = {0.0, 0.0, 0.0};
-    double ke = 0.0;
-    double irho = frcp(rho);
+    const double rho = q[c];
+    double mom[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-        u[d] = q[(1 + d) * N + c] * irho;
-        ke += u[d] * u[d];
-    }
-    ke *= 0.5 * rho;
-    double E = q[iE * N + c];
-    double a = q[iA * N + c];
-    double oma = 1.0 - a;
-    double pl = ph.gm1 * (E - ke) / oma - ph.gpi;
-    double rhol = rho / oma;
-    double cs = sqrt(ph.gamma * (pl + ph.pi_inf) / rhol);
-    double n = 0.0, B = 0.0, Sa = 0.0;
-    double M3 = 0.0, M2d = 0.0, Mp = 0.0, Mk = 0.0;
-    bool bad = !(rho > 0.0) || !(a >= 0.0 && a < 1.0) || !(pl + ph.pi_inf > 0.0) || !(cs < 1e300);
+    for (int d = 0; d < D; ++d) mom[d] = q[(1 + d) * N + c];
+    const double E = q[(D + 1) * N + c];
+    const double a = q[(D + 2) * N + c];
+    const CellCore<D> k = cell_core<D>(rho, mom, E, a, ph);
+    const CellBins m = cell_bins(rho, a, t, ph, bins);
+    bool bad = k.bad || !(m.B == m.B) || !(m.n == m.n);
     const bool negr = a > 0.0 && t.bad < nb;
-    if (a > 0.0) {
-        n = sqrt(FOUR_PI_3 * t.s3 / a);
-        double in = frcp(n);
-        double in2 = in * in, in3 = in2 * in;
-        M3 = t.s3 * in3;
-        M2d = t.s21 * in3;
-        Mk = t.s32 * in3 * in2;
-        Mp = exp2((ph.kappa3 - 3.0) * log2(n)) * t.sp - ph.mu4 * M2d - ph.sigma2 * t.s2 * in2;
-        double iM3 = frcp(M3);
-        B = (Mp - rho * Mk) * iM3;
-        Sa = 3.0 * a * M2d * iM3;
-    } else {
-        for (int i = 0; i < nb; ++i) {
-            double r = bins.r0[i];
-            M3 += bins.w[i] * r * r * r;
-        }
-    }
-    if (!(B == B) || !(n == n)) bad = true;
     if (negr) raise_error(sc, E_NEGR, c, t.bad);   // a negative radius also makes B non-finite
     else if (bad) raise_error(sc, E_NONFINITE, c, -1);
+    double wmax = 0.0;
     if (MODE == PRIM_MOMENTS) {
-        out[0 * N + c] = n;
+        out[0 * N + c] = m.n;
         out[1 * N + c] = a;
-        out[2 * N + c] = M3;
-        out[3 * N + c] = M2d;
-        out[4 * N + c] = Mp;
-        out[5 * N + c] = Mk;
-        out[6 * N + c] = oma * pl + a * B;
-        out[7 * N + c] = pl;
+        out[2 * N + c] = m.M3;
+        out[3 * N + c] = m.M2d;
+        out[4 * N + c] = m.Mp;
+        out[5 * N + c] = m.Mk;
+        out[6 * N + c] = (1.0 - a) * k.pl + a * m.B;
+        out[7 * N + c] = k.pl;
     } else {
         out[PL<D>::RHO * N + c] = rho;
 #pragma unroll
-        for (int d = 0; d < D; ++d) out[(PL<D>::U + d) * N + c] = u[d];
-        out[PL<D>::PLQ * N + c] = pl;
+        for (int d = 0; d < D; ++d) out[(PL<D>::U + d) * N + c] = k.u[d];
+        out[PL<D>::PLQ * N + c] = k.pl;
         out[PL<D>::A * N + c] = a;
-        out[PL<D>::N * N + c] = n;
-        out[PL<D>::B * N + c] = B;
-        out[PL<D>::SA * N + c] = Sa;
+        out[PL<D>::N * N + c] = m.n;
+        out[PL<D>::B * N + c] = m.B;
+        out[PL<D>::SA * N + c] = m.Sa;
         if (MODE == PRIM_CFL) {
 #pragma unroll
-            for (int d = 0; d < D; ++d) wmax = dmax(wmax, (fabs(u[d]) + cs) * g.inv_dx[d]);
+            for (int d = 0; d < D; ++d) wmax = dmax(wmax, (fabs(k.u[d]) + k.cs) * g.inv_dx[d]);
         }
     }
     return wmax;
@@ -166,20 +208,23 @@ __device__ inline void cfl_reduce(double wmax, Scalars *sc) { wmax_post(wmax, sc
 // counter; the slot that arrives last finishes the cell from the sums taken in slot order, so
 // waves that are done leave without waiting for the others.  S = 1 is one thread per cell (large
 // grids, which fill the chip on cells alone).
+// Block `blk` of the pass (cells blk*CELLS ..); every thread of the workgroup calls it.  s_pp: the
+// power's constant table in LDS, filled by the caller before a barrier.
 template <int D, int MODE, int S, int CELLS>
-__global__ void __launch_bounds__(S * CELLS) k_prim(const double *__restrict__ q, double *__restrict__ out,
-                                                    Grid g, Phys ph, Bins bins, Scalars *sc)
+__device__ __forceinline__ void prim_block(const double *__restrict__ q, double *__restrict__ out, const Grid &g,
+                                           const Phys &ph, const Bins &bins, Scalars *sc, long long blk,
+                                           const double *__restrict__ s_pp)
 {
     const int cl = S == 1 ? (int)threadIdx.x : (int)threadIdx.x % CELLS;
     const int slot = S == 1 ? 0 : (int)threadIdx.x / CELLS;
     const long long N = g.N;
-    const long long c = (long long)blockIdx.x * CELLS + cl;
+    const long long c = blk * CELLS + cl;
     const bool live = c < N;
     double wmax = 0.0;
     if constexpr (S == 1) {
         BinSums p;
         p.bad = bins.nb;
-        if (live && q[(D + 2) * N + c] > 0.0) p = bin_sums<D>(q, ph, bins, N, c, 0, 1);
+        if (live && q[(D + 2) * N + c] > 0.0) p = bin_sums<D>(q, ph, bins, N, c, 0, 1, s_pp);
         if (live) wmax = prim_finish<D, MODE>(q, out, g, ph, bins, sc, c, p);
     } else {
         __shared__ double s_sum[5][S][CELLS];
@@ -189,7 +234,7 @@ __global__ void __launch_bounds__(S * CELLS) k_prim(const double *__restrict__ q
         __syncthreads();
         BinSums p;
         p.bad = bins.nb;
-        if (live && q[(D + 2) * N + c] > 0.0) p = bin_sums<D>(q, ph, bins, N, c, slot, S);
+        if (live && q[(D + 2) * N + c] > 0.0) p = bin_sums<D>(q, ph, bins, N, c, slot, S, s_pp);
         s_sum[0][slot][cl] = p.s3;
         s_sum[1][slot][cl] = p.s2;
         s_sum[2][slot][cl] = p.s21;
@@ -215,6 +260,16 @@ __global__ void __launch_bounds__(S * CELLS) k_prim(const double *__restrict__ q
         }
     }
     if (MODE == PRIM_CFL) cfl_reduce(wmax, sc);
+}
+
+template <int D, int MODE, int S, int CELLS>
+__global__ void __launch_bounds__(S * CELLS) k_prim(const double *__restrict__ q, double *__restrict__ out,
+                                                    Grid g, Phys ph, Bins bins, Scalars *sc)
+{
+    __shared__ double s_pp[PPOW_N];   // constants of the polytropic power
+    if (threadIdx.x < PPOW_N) s_pp[threadIdx.x] = PPOW_TABLE[threadIdx.x];
+    __syncthreads();
+    prim_block<D, MODE, S, CELLS>(q, out, g, ph, bins, sc, blockIdx.x, s_pp);
 }
 
 // Threads per cell for a grid of N cells: enough to give about 2^19 threads, at most PRIM_SLOTS.
@@ -257,7 +312,7 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ prim, d
 
 // Time step from the wave-speed max (or a fixed value); clears the partial maxima for the next
 // step.  One wave of WMAX_SLOTS threads.
-__global__ void __launch_bounds__(WMAX_SLOTS) k_dt(Scalars *sc, double fixed_dt, double cfl, double *user_dt)
+__device__ __forceinline__ void dt_block(Scalars *sc, double fixed_dt, double cfl, double *user_dt)
 {
     const int i = threadIdx.x;
     unsigned long long m = sc->wmax[i * WMAX_STRIDE];
@@ -272,6 +327,11 @@ __global__ void __launch_bounds__(WMAX_SLOTS) k_dt(Scalars *sc, double fixed_dt,
         sc->dt = dt;
         if (user_dt) *user_dt = dt;
     }
+}
+
+__global__ void __launch_bounds__(WMAX_SLOTS) k_dt(Scalars *sc, double fixed_dt, double cfl, double *user_dt)
+{
+    dt_block(sc, fixed_dt, cfl, user_dt);
 }
 
 

@@ -69,13 +69,15 @@ __device__ inline int bubble_bin(const Phys &ph, double &y0, double &y1, double 
 // slots first pool sum w (nR)^3 for n (one barrier), then each advances its bins, posts its part
 // of sum w R^3 before and after, and bumps the cell's LDS counter; the slot that arrives last
 // updates alpha, so waves whose bins need fewer sub-steps leave without waiting.
+// Block `blk` of the half-step (cells blk*CELLS ..); every thread of the workgroup calls it.
 template <int D, int S, int CELLS>
-__global__ void __launch_bounds__(S * CELLS) k_bubble(BubbleArgs A, Grid g, Phys ph, Bins bins, Scalars *sc)
+__device__ __forceinline__ void bubble_block(const BubbleArgs &A, const Grid &g, const Phys &ph, const Bins &bins,
+                                             Scalars *sc, long long blk)
 {
     const int cl = S == 1 ? (int)threadIdx.x : (int)threadIdx.x % CELLS;
     const int slot = S == 1 ? 0 : (int)threadIdx.x / CELLS;
     const long long N = g.N;
-    const long long c = (long long)blockIdx.x * CELLS + cl;
+    const long long c = blk * CELLS + cl;
     const bool live = c < N;
     const int nb = bins.nb;
     const int iE = D + 1, iA = D + 2, iNR = D + 3, iNV = D + 3 + nb;
@@ -159,6 +161,12 @@ __global__ void __launch_bounds__(S * CELLS) k_bubble(BubbleArgs A, Grid g, Phys
             q[iA * N + c] = a * mn / mo;
         }
     }
+}
+
+template <int D, int S, int CELLS>
+__global__ void __launch_bounds__(S * CELLS) k_bubble(BubbleArgs A, Grid g, Phys ph, Bins bins, Scalars *sc)
+{
+    bubble_block<D, S, CELLS>(A, g, ph, bins, sc, blockIdx.x);
 }
 
 }  // namespace bub

@@ -117,6 +117,12 @@ struct StageArgs {
     int ngroups;        // workgroups per tile, each taking a contiguous range of bpg bins
     int bpg;            // bins per group (ngroups * bpg >= nb)
     int nitems;         // ntiles * ngroups
+    // Fused primitive pass (RK mode, one workgroup per tile): the epilogue writes the primitives of
+    // the state it produces into Pout (the layout of P; must not be P) and, with cfl set, posts that
+    // state's wave-speed maximum.  Null Pout: the next stage needs a primitive pass of its own.
+    double *Pout;
+    int cfl;
+    Scalars *sc;        // error word and wave-speed maxima of the context
 };
 
 // LDS needs of one tile: coef[F] and scr[SCR] of TF, flag[F] bytes.
@@ -130,8 +136,9 @@ struct StageLds {
     static constexpr int BYTES = (G::F + SCR) * (int)sizeof(TF) + G::F;
 };
 
-// The work of one tile (every thread of the workgroup calls it).
-template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF>
+// The work of one tile (every thread of the workgroup calls it).  FUSE: the epilogue carries the
+// primitive pass of the state it writes (A.Pout, A.cfl).
+template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF, bool FUSE>
 // Bins b0 <= ib < b1 are this workgroup's; core_out: it also writes the mixture variables
 // (exactly one workgroup per tile does).
 __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, const Phys &ph, const Bins &bins,
@@ -310,6 +317,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
     }
     const double dt = A.rhs_mode ? 0.0 : *A.dtp;
     double own_n = 0.0, own_in = 0.0, own_pl = 0.0, own_irhol = 1.0, own_ic = 1.0;
+    // fused primitive pass: the owned cell's new rho and alpha, admissibility, wave speed, bin sums
+    constexpr bool fuse = FUSE;
+    double new_rho = 0.0, new_a = 0.0, wcfl = 0.0;
+    bool new_bad = false;
+    BinSums acc;
+    acc.bad = nb;
     if (active && core_out) {
         TF Lc[NCF];
 #pragma unroll
@@ -319,6 +332,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
             for (int d = 0; d < D; ++d) acc += (s_cf[v * F + flo[d]] - s_cf[v * F + fhi[d]]) * (TF)g.inv_dx[d];
             Lc[v] = acc;
         }
+        double nq[NCF];
 #pragma unroll
         for (int v = 0; v < NCF; ++v) {
             long long o = (long long)v * N + gc;
@@ -329,6 +343,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
                 double r = A.b * (A.qk[o] + dt * Lv);
                 if (A.a != 0.0) r += A.a * A.qn[o];
                 A.qo[o] = r;
+                nq[v] = r;
+            }
+        }
+        if constexpr (fuse) {
+            const CellCore<D> k = cell_core<D>(nq[0], &nq[1], nq[D + 1], nq[D + 2], ph);
+            A.Pout[PL<D>::RHO * N + gc] = nq[0];
+#pragma unroll
+            for (int d = 0; d < D; ++d) A.Pout[(PL<D>::U + d) * N + gc] = k.u[d];
+            A.Pout[PL<D>::PLQ * N + gc] = k.pl;
+            A.Pout[PL<D>::A * N + gc] = nq[D + 2];
+            new_rho = nq[0];
+            new_a = nq[D + 2];
+            new_bad = k.bad;
+            if (A.cfl) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) wcfl = dmax(wcfl, (fabs(k.u[d]) + k.cs) * g.inv_dx[d]);
             }
         }
     }
@@ -357,7 +387,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
     // faster in 3D; in 2D the extra registers cost a wave per SIMD, so it stores at once).
     constexpr bool DEFER = D == 3;
     for (int ib = b0; ib < b1; ++ib) {
-        const double r0 = bins.r0[ib];
+        const double r0 = bins.r0[ib], pg0 = bins.pg0[ib];
         const double own_r = pre_r[0], own_v = pre_v[0], own_nr = pre_nr, own_nv = pre_nv;
 #pragma unroll
         for (int r = 0; r < CPT; ++r) {
@@ -449,7 +479,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
                 // Keller--Miksis in FP64 from the FP64 state of the owned cell
                 double own_R = xr0 * own_in, own_V = xv0 * own_in;
                 LR += own_n * own_V;
-                LV += own_n * km_rddot_t(ph, own_R, own_V, r0, bins.pg0[ib], own_pl, own_irhol, own_ic, s_pp);
+                LV += own_n * km_rddot_t(ph, own_R, own_V, r0, pg0, own_pl, own_irhol, own_ic, s_pp);
             }
             double xr = LR, xv = LV;
             if (!A.rhs_mode) {
@@ -460,6 +490,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
                     xv += A.a * own_nv;
                 }
             }
+            if constexpr (fuse) bin_add(acc, ib, xr, xv, bins.w[ib], pg0, r0, nb, ph, s_pp);
             if constexpr (DEFER) {
                 s_out[tid] = xr;
                 s_out[BLOCK + tid] = xv;
@@ -475,30 +506,56 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
         A.qo[(long long)(iNR + b1 - 1) * N + gc] = s_out[tid];
         A.qo[(long long)(iNV + b1 - 1) * N + gc] = s_out[BLOCK + tid];
     }
+    if constexpr (fuse) {
+        // the primitive pass of the new state for the owned cell (same arithmetic as k_prim)
+        if (active) {
+            const CellBins m = cell_bins(new_rho, new_a, acc, ph, bins);
+            A.Pout[PL<D>::N * N + gc] = m.n;
+            A.Pout[PL<D>::B * N + gc] = m.B;
+            A.Pout[PL<D>::SA * N + gc] = m.Sa;
+            const bool bad = new_bad || !(m.B == m.B) || !(m.n == m.n);
+            if (new_a > 0.0 && acc.bad < nb) raise_error(A.sc, E_NEGR, gc, acc.bad);
+            else if (bad) raise_error(A.sc, E_NONFINITE, gc, -1);
+        }
+        if (A.cfl) wmax_post(wcfl, A.sc);
+    }
     __syncthreads();  // a following tile on this workgroup may reuse the LDS at once
 }
 
-// The 1D and 2D kernels of the mixed form fit 96 VGPRs without spilling and run five waves per
-// SIMD (2D: 4 % faster stage than at four); the FP64 ones would spill.
-template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((D <= 2 && sizeof(TF) == 4) ? 5 : 1))) k_stage(StageArgs A, Grid g, Phys ph, Bins bins)
+// The unfused 1D and 2D kernels of the mixed form fit 96 VGPRs without spilling and run five waves
+// per SIMD (2D: 4 % faster stage than at four); the FP64 ones, and the fused ones, would spill.
+// The LDS arrays of one stage workgroup, declared in the kernel that uses them.
+#define BUB_STAGE_SHARED(D, TX_, TY_, TZ_, BLOCK, TF)                                   \
+    __shared__ TF s_coef[Geo<D, TX_, TY_, TZ_>::F];                                       \
+    __shared__ TF s_scr[StageLds<D, TX_, TY_, TZ_, TF>::SCR];                             \
+    __shared__ unsigned char s_flag[Geo<D, TX_, TY_, TZ_>::F];                            \
+    __shared__ double s_out[D == 3 ? 2 * BLOCK : 1]; /* 3D: results stored one bin late */ \
+    __shared__ double s_pp[PPOW_N];                  /* constants of the polytropic power */ \
+    if (threadIdx.x < PPOW_N) s_pp[threadIdx.x] = PPOW_TABLE[threadIdx.x]; /* read after the tile's barriers */
+
+// Work item `item` (a tile, or one bin group of a tile) of a stage.
+template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF, bool FUSE>
+__device__ __forceinline__ void stage_item(const StageArgs &A, const Grid &g, const Phys &ph, const Bins &bins,
+                                           int item, TF *__restrict__ s_coef, TF *__restrict__ s_scr,
+                                           unsigned char *__restrict__ s_flag, double *__restrict__ s_out,
+                                           const double *__restrict__ s_pp)
 {
-    using G = Geo<D, TX_, TY_, TZ_>;
-    using S = StageLds<D, TX_, TY_, TZ_, TF>;
-    __shared__ TF s_coef[G::F];
-    __shared__ TF s_scr[S::SCR];
-    __shared__ unsigned char s_flag[G::F];
-    __shared__ double s_out[D == 3 ? 2 * BLOCK : 1];   // 3D: results stored one bin late
-    __shared__ double s_pp[PPOW_N];                     // constants of the polytropic power
-    if (threadIdx.x < PPOW_N) s_pp[threadIdx.x] = PPOW_TABLE[threadIdx.x];   // read after the tile's barriers
+    const int tile = item / A.ngroups, grp = item - tile * A.ngroups;
+    const int b0 = grp * A.bpg, b1 = b0 + A.bpg < bins.nb ? b0 + A.bpg : bins.nb;
+    stage_tile<D, TX_, TY_, TZ_, BLOCK, TF, FUSE>(A, g, ph, bins, tile, b0, b1, grp == 0, s_coef, s_scr, s_flag, s_out,
+                                                  s_pp);
+}
+
+template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF, bool FUSE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((D <= 2 && sizeof(TF) == 4 && !FUSE) ? 5 : 1))) k_stage(StageArgs A, Grid g, Phys ph, Bins bins)
+{
+    BUB_STAGE_SHARED(D, TX_, TY_, TZ_, BLOCK, TF)
     // XCD-aware order: consecutive items land on the same XCD (blocks are dealt round-robin), and
     // the bin groups of a tile are consecutive items, so they share that XCD's L2.
     const int b = blockIdx.x;
     const int item = (b & 7) * A.nblk_per_xcd + (b >> 3);
     if (item >= A.nitems) return;
-    const int tile = item / A.ngroups, grp = item - tile * A.ngroups;
-    const int b0 = grp * A.bpg, b1 = b0 + A.bpg < bins.nb ? b0 + A.bpg : bins.nb;
-    stage_tile<D, TX_, TY_, TZ_, BLOCK, TF>(A, g, ph, bins, tile, b0, b1, grp == 0, s_coef, s_scr, s_flag, s_out, s_pp);
+    stage_item<D, TX_, TY_, TZ_, BLOCK, TF, FUSE>(A, g, ph, bins, item, s_coef, s_scr, s_flag, s_out, s_pp);
 }
 
 }  // namespace bub

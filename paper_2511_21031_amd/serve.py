@@ -35,10 +35,12 @@ import numpy as np
 
 def footprint_bytes(case) -> int:
     """Device bytes a problem holds while resident: its state, the two work copies of the
-    stage results, and the context's own buffers (plus alignment slack)."""
+    stage results, the context's own buffers (plus alignment slack), and the device copy of its
+    initial primitives ([ndim+3][N] doubles), which stays alive until the problem retires because
+    the state is built from it asynchronously."""
     from ._binding import ctx_buffer_bytes
     state = 8 * case.nvar * case.ncells
-    return 3 * state + ctx_buffer_bytes(case.ndim, case.n, case.nb) + 256
+    return 3 * state + ctx_buffer_bytes(case.ndim, case.n, case.nb) + 256 + 8 * (case.ndim + 3) * case.ncells
 
 
 @dataclass

@@ -55,3 +55,22 @@ def rhs_err(got, ref, scale):
     ref = np.asarray(ref)
     s = np.abs(ref).max(axis=-1) + scale
     return np.abs(got - ref).max(axis=-1) / np.maximum(s, 1e-300)
+
+
+def oracle_split_step(orc, pb, q, dt):
+    """One split-mode step of the oracle in its three parts, S_b(dt/2) S_f(dt) S_b(dt/2), in place on q.
+
+    Returns the accepted sub-step counts of both bubble half-steps, int32 [2][nb][N].  The flux part is
+    the oracle's SSP-RK3 on its flux-only right-hand side with the same operations in the same order as
+    the oracle's own step, so the result is bitwise that of orc.rk3_step (a CPU test checks this).
+    """
+    ns1 = orc.bubble_advance(pb, q, 0.5 * dt)
+    L = orc.rhs(pb, q, sources=False)
+    u1 = q + dt * L
+    L = orc.rhs(pb, u1, sources=False)
+    u2 = 0.75 * q + 0.25 * (u1 + dt * L)
+    L = orc.rhs(pb, u2, sources=False)
+    q[:] = q / 3.0 + 2.0 / 3.0 * (u2 + dt * L)
+    ns2 = orc.bubble_advance(pb, q, 0.5 * dt)
+    return np.stack([ns1, ns2])
+

@@ -218,21 +218,59 @@ def test_error_word_nonfinite_and_negative_radius(torch, bub, orc):
     assert code == -5 and cell == 40 and b == 1
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("kind", ["c1", "2d_ragged_periodic", "3d_ragged_reflective"])
-def test_tile_shapes_give_identical_results(torch, bub, orc, kind):
-    """Every compiled tile shape computes each face flux with the same arithmetic: bitwise equal RHS."""
+def test_tile_shapes_give_identical_results(torch, bub, orc, kind, prec):
+    """Every compiled tile shape (the autotuner's candidates, in both precisions) computes each face
+    flux with the same arithmetic: bitwise equal right-hand sides and RK3 steps."""
     case = _case_grid(kind)
     pb = orc.problem_from_case(case)
-    q = _gpu(torch, perturb_bins(orc.init_state(pb, case.prim), case.ndim, case.nb, seed=4))
-    ctx = bub.context_from_case(case)
+    q0 = _gpu(torch, perturb_bins(orc.init_state(pb, case.prim), case.ndim, case.nb, seed=4))
+    P = bub.PREC_FP64 if prec == "fp64" else bub.PREC_MIXED
+    ctx = bub.context_from_case(case, precision=P)
+    work = ctx.new_work()
     outs = []
     for v in range(len(ctx.tiles())):
         ctx.tile = v
-        outs.append(ctx.rhs_stage(q).cpu().numpy())
-    for o in outs[1:]:
-        assert np.array_equal(o, outs[0])
-    best, ms = ctx.autotune(q, reps=2)
+        q = q0.clone()
+        rhs = ctx.rhs_stage(q)
+        for _ in range(3):
+            ctx.rk3_step(q, work)
+        assert ctx.last_error()[0] == 0
+        outs.append((rhs.cpu().numpy(), q.cpu().numpy()))
+    for v, (r, st) in enumerate(outs[1:], 1):
+        assert np.array_equal(r, outs[0][0]), (prec, ctx.tiles()[v])
+        assert np.array_equal(st, outs[0][1]), (prec, ctx.tiles()[v])
+    best, ms = ctx.autotune(q0, reps=2)
     assert ctx.tile == best and 0 <= best < len(ms) and all(m > 0 for m in ms)
+
+
+@pytest.mark.timeout(900)
+def test_c2_shaped_fp64_trajectory(torch, bub, orc):
+    """The benchmark's recipe at 256^2 (31 bins, sigma 0.5, periodic, 1 atm plane wave), 100 RK3 steps of
+    plain FP64 with the device's own CFL step: every field within 1e-10 (max-norm relative) of the oracle,
+    or within 10x the oracle's own drift under a 2e-16 perturbation of its start where that is larger."""
+    case = W.c2(n=256)
+    pb = orc.problem_from_case(case)
+    q_ref = orc.init_state(pb, case.prim)
+    q_pert = q_ref * (1.0 + 2e-16 * np.random.default_rng(98).standard_normal(q_ref.shape))
+    ctx = bub.context_from_case(case)
+    q = ctx.init_state(_gpu(torch, case.prim))
+    work = ctx.new_work()
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(100):
+        dt = orc.cfl_dt(pb, q_ref)
+        orc.rk3_step(pb, q_ref, dt)
+        orc.rk3_step(pb, q_pert, dt)
+        ctx.rk3_step(q, work, 0.0, dt_dev)
+        assert abs(dt_dev.item() / dt - 1) < 1e-12
+    assert ctx.last_error()[0] == 0
+    got = q.cpu().numpy()
+    err, env = rel_err(got, q_ref), rel_err(q_pert, q_ref)
+    print(f"256^2 x 31 bins, 100 steps: max field err {err.max():.3e} (oracle drift {env.max():.3e})")
+    assert np.all(err <= np.maximum(1e-10, 10 * env)), (err.max(), env.max())
+    mg, mr = orc.moments(pb, got), orc.moments(pb, q_ref)
+    assert rel_err(mg[[1, 6]], mr[[1, 6]]).max() < 1e-10   # alpha and the mixture pressure
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -256,3 +294,71 @@ def test_bin_groups_give_identical_results(torch, bub, orc, kind, prec):
         outs.append((rhs.cpu().numpy(), q.cpu().numpy()))
     for r, s in outs[1:]:
         assert np.array_equal(r, outs[0][0]) and np.array_equal(s, outs[0][1])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape", [(1024, 512, 1), (84, 84, 84)])
+def test_fused_primitive_pass_is_bitwise_the_separate_pass(torch, bub, orc, shape, prec):
+    """From 2^19 cells on, stages 1 and 2 write the next stage's primitives from their epilogue; two
+    workgroups per tile (forced) take the separate primitive pass instead.  Same arithmetic, same bin
+    order: the steps must agree bit for bit (right-hand sides and states)."""
+    ndim = 2 if shape[2] == 1 else 3
+    n = shape[:ndim]
+    case = W.random_smooth(ndim, n, 1e-4, 5, seed=31, bc=1 if ndim == 3 else 0)
+    pb = orc.problem_from_case(case)
+    q0 = _gpu(torch, perturb_bins(orc.init_state(pb, case.prim), ndim, 5, seed=5))
+    P = bub.PREC_FP64 if prec == "fp64" else bub.PREC_MIXED
+    outs = []
+    for groups in (0, 2):
+        ctx = bub.context_from_case(case, precision=P)
+        ctx.set_bin_groups(groups)
+        q = q0.clone()
+        work = ctx.new_work()
+        for _ in range(2):
+            ctx.rk3_step(q, work)
+        assert ctx.last_error()[0] == 0
+        outs.append(q.cpu().numpy())
+        del ctx, work
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_fused_steps_match_oracle(torch, bub, orc):
+    """Fused stages at 1024 x 512 (5 bins, periodic, perturbed bins): 3 RK3 steps against the oracle."""
+    case = W.random_smooth(2, (1024, 512), 1e-4, 5, seed=32)
+    pb = orc.problem_from_case(case)
+    qh = perturb_bins(orc.init_state(pb, case.prim), 2, 5, seed=6)
+    q_ref, q_pert = qh.copy(), qh * (1.0 + 2e-16 * np.random.default_rng(97).standard_normal(qh.shape))
+    ctx = bub.context_from_case(case)
+    q = _gpu(torch, qh)
+    work = ctx.new_work()
+    for _ in range(3):
+        dt = orc.cfl_dt(pb, q_ref)
+        orc.rk3_step(pb, q_ref, dt)
+        orc.rk3_step(pb, q_pert, dt)
+        ctx.rk3_step(q, work, dt)
+    assert ctx.last_error()[0] == 0
+    err, env = rel_err(q.cpu().numpy(), q_ref), rel_err(q_pert, q_ref)
+    print(f"fused 1024x512 x 5 bins, 3 steps: max field err {err.max():.3e} (oracle drift {env.max():.3e})")
+    assert np.all(err <= np.maximum(1e-10, 10 * env))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_rk3_steps_is_bitwise_repeated_steps(torch, bub, orc, prec):
+    """rk3_steps(n) carries the primitives and wave speeds of each step's result to the next step from
+    the third stage's epilogue; the states and time steps must be those of n separate calls, bit for bit."""
+    case = W.random_smooth(2, (1024, 520), 1e-4, 3, seed=33)
+    pb = orc.problem_from_case(case)
+    q0 = _gpu(torch, perturb_bins(orc.init_state(pb, case.prim), 2, 3, seed=7))
+    P = bub.PREC_FP64 if prec == "fp64" else bub.PREC_MIXED
+    ctx = bub.context_from_case(case, precision=P)
+    work = ctx.new_work()
+    dts = torch.zeros(4, dtype=torch.float64, device="cuda")
+    qa = q0.clone()
+    for k in range(4):
+        ctx.rk3_step(qa, work, 0.0, dts[k:k + 1])
+    qb = q0.clone()
+    dtb = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.rk3_steps(qb, work, 4, 0.0, dtb)
+    assert ctx.last_error()[0] == 0
+    assert torch.equal(qa, qb)
+    assert dtb.item() == dts[3].item() and dts.min().item() > 0

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.parity import flux_scale, perturb_bins, rel_err, rhs_err
+from tests.parity import flux_scale, oracle_split_step, perturb_bins, rel_err, rhs_err
 
 pytestmark = pytest.mark.gpu
 RTOL = 1e-4
@@ -52,6 +52,41 @@ def _compare_advance(q_gpu, q_ref, ns_gpu, ns_ref, ndim, nb):
     return 1.0 - same.mean()
 
 
+def _split_trajectory(torch, bub, orc, case, steps):
+    """Both sides step `case` in split mode with the oracle's steps; returns the GPU and oracle states and
+    the number of (cell, bin, half-step) sub-step counts that differed between the two sides."""
+    pb = orc.problem_from_case(case, split=1)
+    q_ref = orc.init_state(pb, case.prim)
+    ctx = bub.context_from_case(case, bubble_mode=bub.BUBBLES_SPLIT)
+    q = ctx.init_state(_gpu(torch, case.prim))
+    work = ctx.new_work()
+    ns = torch.zeros((2, case.nb, case.ncells), dtype=torch.int32, device="cuda")
+    ctx.substep_counts(ns)
+    diverged = 0
+    for _ in range(steps):
+        dt = orc.cfl_dt(pb, q_ref)
+        ns_ref = oracle_split_step(orc, pb, q_ref, dt)
+        ctx.rk3_step(q, work, dt)
+        diverged += int((ns.cpu().numpy() != ns_ref).sum())
+    ctx.substep_counts(None)
+    assert ctx.last_error()[0] == 0
+    return pb, q.cpu().numpy(), q_ref, diverged
+
+
+def _judge_split(orc, pb, got, q_ref, diverged, tag):
+    """1e-8 on every field when no sub-step decision differed anywhere in the run, else 10 rtol."""
+    err = rel_err(got, q_ref)
+    mg, mr = orc.moments(pb, got), orc.moments(pb, q_ref)
+    e_p, e_a = rel_err(mg[6], mr[6]), rel_err(mg[1], mr[1])
+    print(f"{tag}: diverging sub-step counts {diverged}; max field err {err.max():.3e}, p {e_p:.3e}, "
+          f"alpha {e_a:.3e}")
+    if diverged == 0:
+        assert err.max() < 1e-8
+    else:
+        assert err.max() < 10 * RTOL
+        assert e_p < 1e-6 and e_a < 10 * RTOL
+
+
 @pytest.mark.parametrize("amp", [3.0, 10.0])
 def test_bubble_advance_matches_oracle(torch, bub, orc, amp):
     case = W.c3(n=12, nb=5, amp_atm=amp, width=4e-4)
@@ -73,24 +108,8 @@ def test_bubble_advance_matches_oracle(torch, bub, orc, amp):
 def test_split_trajectory_3d_pulse(torch, bub, orc):
     """A 10 atm spherical pulse that collapses bubbles: unsplit RK3 fails, split mode advances."""
     case = W.c3(n=24, nb=5, width=6e-4)
-    pb = orc.problem_from_case(case, split=1)
-    q_ref = orc.init_state(pb, case.prim)
-    ctx = bub.context_from_case(case, bubble_mode=bub.BUBBLES_SPLIT)
-    q = ctx.init_state(_gpu(torch, case.prim))
-    work = ctx.new_work()
-    for _ in range(8):
-        dt = orc.cfl_dt(pb, q_ref)
-        orc.rk3_step(pb, q_ref, dt)
-        ctx.rk3_step(q, work, dt)
-    assert ctx.last_error()[0] == 0
-    got = q.cpu().numpy()
-    err = rel_err(got, q_ref)
-    mg, mr = orc.moments(pb, got), orc.moments(pb, q_ref)
-    e_p = rel_err(mg[6], mr[6])
-    e_a = rel_err(mg[1], mr[1])
-    print("split 3D: max field err", err.max(), "p", e_p, "alpha", e_a)
-    assert err.max() < 10 * RTOL
-    assert e_p < 1e-6 and e_a < 10 * RTOL
+    pb, got, q_ref, diverged = _split_trajectory(torch, bub, orc, case, 8)
+    _judge_split(orc, pb, got, q_ref, diverged, "split 3D pulse 24^3 nb 5, 8 steps")
 
 
 def test_full_size_3d_sampled(torch, bub, orc):
@@ -147,21 +166,5 @@ def _serving_requests():
 @pytest.mark.parametrize("kind", ["1d", "2d"])
 def test_split_trajectory_1d_2d_requests(torch, bub, orc, kind):
     case = _serving_requests()[kind]
-    pb = orc.problem_from_case(case, split=1)
-    q_ref = orc.init_state(pb, case.prim)
-    ctx = bub.context_from_case(case, bubble_mode=bub.BUBBLES_SPLIT)
-    q = ctx.init_state(_gpu(torch, case.prim))
-    work = ctx.new_work()
-    for _ in range(6):
-        dt = orc.cfl_dt(pb, q_ref)
-        orc.rk3_step(pb, q_ref, dt)
-        ctx.rk3_step(q, work, dt)
-    assert ctx.last_error()[0] == 0
-    got = q.cpu().numpy()
-    err = rel_err(got, q_ref)
-    mg, mr = orc.moments(pb, got), orc.moments(pb, q_ref)
-    e_p = rel_err(mg[6], mr[6])
-    e_a = rel_err(mg[1], mr[1])
-    print(f"split {kind} {case.n} nb {case.nb}: max field err", err.max(), "p", e_p, "alpha", e_a)
-    assert err.max() < 10 * RTOL
-    assert e_p < 1e-6 and e_a < 10 * RTOL
+    pb, got, q_ref, diverged = _split_trajectory(torch, bub, orc, case, 6)
+    _judge_split(orc, pb, got, q_ref, diverged, f"split {kind} {case.n} nb {case.nb}, 6 steps")

@@ -93,10 +93,21 @@ def test_ctx_buffer_bytes_host_only(L):
     assert L.bub_ctx_buffer_bytes(None, ctypes.byref(bn), ctypes.byref(out)) == -1
 
 
-def test_serving_footprint_counts_three_states_and_the_context(L):
+def test_serving_footprint_counts_three_states_the_context_and_the_primitives(L):
     import workloads as W
+    from paper_2511_21031_amd import ctx_buffer_bytes
     from paper_2511_21031_amd.serve import footprint_bytes
     case = W.request_case(W.c5_stream(count=1, seed=3)[0])
     fp = footprint_bytes(case)
     state = 8 * case.nvar * case.ncells
-    assert 3 * state < fp < 3 * state + 8 * (case.ndim + 6) * case.ncells + 16384
+    prim = 8 * (case.ndim + 3) * case.ncells      # the initial primitives, alive until the problem retires
+    ctxb = ctx_buffer_bytes(case.ndim, case.n, case.nb)
+    assert 3 * state + prim + ctxb <= fp <= 3 * state + prim + ctxb + 256
+
+
+def test_context_buffer_holds_a_second_primitive_scratch_from_2_19_cells(L):
+    from paper_2511_21031_amd import ctx_buffer_bytes
+    small, big = ctx_buffer_bytes(2, (724, 724, 1), 5), ctx_buffer_bytes(2, (725, 725, 1), 5)
+    p_small, p_big = 8 * 8 * 724 * 724, 8 * 8 * 725 * 725          # (ndim + 6) fields
+    assert p_small < small < p_small + 16384                          # 524176 cells: one scratch
+    assert 2 * p_big < big < 2 * p_big + 16384                        # 525625 cells: two

@@ -295,3 +295,20 @@ def test_el_frozen_alpha_sound_speed(orc, alpha):
     tz = ts[i] - amps[i] * (ts[i + 1] - ts[i]) / (amps[i + 1] - amps[i])
     c_meas = math.pi / 2 / tz / k
     assert abs(c_meas / c - 1) < 2e-6, (c_meas, c)
+
+
+def test_split_step_in_parts_is_bitwise_the_oracle_step(orc):
+    """The tests' three-part split step (used to see both half-steps' sub-step counts) is the oracle's
+    own split step, bit for bit."""
+    import workloads as W
+    from tests.parity import oracle_split_step
+    case = W.c3(n=10, nb=3, width=5e-4)
+    pb = orc.problem_from_case(case, split=1)
+    q1 = orc.init_state(pb, case.prim)
+    q2 = q1.copy()
+    for _ in range(3):
+        dt = orc.cfl_dt(pb, q1)
+        orc.rk3_step(pb, q1, dt)
+        ns = oracle_split_step(orc, pb, q2, dt)
+        assert ns.shape == (2, 3, q1.shape[1]) and ns.min() >= 1
+        assert np.array_equal(q1, q2)
