@@ -43,7 +43,10 @@ class Problem(ctypes.Structure):
         ("pv", ctypes.c_double),
         ("nb", ctypes.c_int), ("r0_median", ctypes.c_double), ("sigma_ln", ctypes.c_double),
         ("cfl", ctypes.c_double), ("split", ctypes.c_int), ("sub_rtol", ctypes.c_double),
-        ("max_substeps", ctypes.c_int),
+        ("max_substeps", ctypes.c_int), ("viscous", ctypes.c_int),
+        ("t", ctypes.c_double), ("src_on", ctypes.c_int), ("src_dir", ctypes.c_int), ("src_sign", ctypes.c_int),
+        ("src_x", ctypes.c_double), ("src_width", ctypes.c_double), ("src_amp", ctypes.c_double),
+        ("src_freq", ctypes.c_double), ("src_t0", ctypes.c_double), ("src_ncyc", ctypes.c_double),
     ]
 
 
@@ -72,6 +75,8 @@ def lib():
         L.orc_km_integrate.argtypes = [P] + [ctypes.c_double] * 10 + [ctypes.c_int, _dp, _dp, _dp,
                                                                          ctypes.c_double, _dp]
         L.orc_km_integrate.restype = ctypes.c_int64
+        L.orc_source_amplitude.argtypes = [P, ctypes.c_double]
+        L.orc_source_amplitude.restype = ctypes.c_double
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_set_threads.argtypes = [ctypes.c_int]
@@ -100,7 +105,8 @@ def _check(rc, what):
 
 
 def problem(ndim, n, dx, bc, nb, r0_median=10e-6, sigma_ln=0.3, cfl=0.3, liquid=None, gas=None,
-            split=0, sub_rtol=1e-4, max_substeps=10000) -> Problem:
+            split=0, sub_rtol=1e-4, max_substeps=10000, viscous=0, source=None, t=0.0) -> Problem:
+    """source: dict(dir, sign, x, width, amp, freq, t0=0, ncyc=0) of the one-way acoustic source."""
     from workloads import WATER, AIR
     liquid = liquid or WATER
     gas = gas or AIR
@@ -120,7 +126,22 @@ def problem(ndim, n, dx, bc, nb, r0_median=10e-6, sigma_ln=0.3, cfl=0.3, liquid=
     pb.split = int(split)
     pb.sub_rtol = sub_rtol
     pb.max_substeps = int(max_substeps)
+    pb.viscous = int(viscous)
+    pb.t = float(t)
+    if source:
+        set_source(pb, **source)
     return pb
+
+
+def set_source(pb, dir, sign, x, width, amp, freq, t0=0.0, ncyc=0.0):
+    pb.src_on = 1
+    pb.src_dir, pb.src_sign = int(dir), int(sign)
+    pb.src_x, pb.src_width, pb.src_amp = float(x), float(width), float(amp)
+    pb.src_freq, pb.src_t0, pb.src_ncyc = float(freq), float(t0), float(ncyc)
+
+
+def source_amplitude(pb, t):
+    return lib().orc_source_amplitude(ctypes.byref(pb), float(t))
 
 
 def problem_from_case(case, **kw) -> Problem:
@@ -188,10 +209,11 @@ def cfl_dt(pb, q):
 
 
 def rk3_step(pb, q, dt=0.0):
-    """Advance q (float64, C-contiguous, modified in place); return the step used."""
+    """Advance q (float64, C-contiguous, modified in place) and the clock pb.t; return the step used."""
     assert q.dtype == np.float64 and q.flags.c_contiguous
     used = ctypes.c_double(0.0)
     _check(lib().orc_rk3_step(ctypes.byref(pb), _ptr(q), float(dt), ctypes.byref(used)), "rk3_step")
+    pb.t += used.value
     return used.value
 
 

@@ -28,6 +28,9 @@
  *                   contact at rest, the exact Sod solution, passive fluxes
  *                   = upwind specific value times mass flux, and a trace void
  *                   fraction following the exact contact.
+ *   viscous stress  eq. stressTensor in eq. euler_transport (optional) --
+ *                   pinned by the analytic divergence of T and T.u for a 2D
+ *                   field at second order, and the decay of a shear wave.
  *   semi-discrete   Sec. 3 eq. (finite-volume form) -- pinned by free-stream
  *                   preservation, discrete conservation, symmetry, 1D = 2D.
  *   SSP-RK3         Sec. 3 (third-order TVD RK) -- pinned by order >= 2.8 on the
@@ -106,11 +109,16 @@ static int setup(const orc_problem *pb, setup_t *s)
         if (d < pb->ndim) {
             if (!(pb->dx[d] > 0.0)) return -1;
             for (int e = 0; e < 2; ++e) {
-                if (pb->bc[d][e] != 0 && pb->bc[d][e] != 1) return -1;
+                if (pb->bc[d][e] < 0 || pb->bc[d][e] > 2) return -1;
                 if (pb->bc[d][e] == 1 && pb->n[d] < 3) return -1;
             }
             if (pb->bc[d][0] != pb->bc[d][1] && (pb->bc[d][0] == 0 || pb->bc[d][1] == 0)) return -1;
         }
+    }
+    if (pb->src_on) {
+        if (pb->src_dir < 0 || pb->src_dir >= pb->ndim || (pb->src_sign != 1 && pb->src_sign != -1)) return -1;
+        if (!(pb->src_width > 0.0) || !(pb->src_freq > 0.0) || !(pb->src_ncyc >= 0.0) || !isfinite(pb->src_amp))
+            return -1;
     }
     s->nd = pb->ndim;
     s->nb = pb->nb;
@@ -137,22 +145,89 @@ static int64_t lin(const orc_problem *pb, int i, int j, int k)
     return (int64_t)i + (int64_t)pb->n[0] * ((int64_t)j + (int64_t)pb->n[1] * k);
 }
 
-/* Ghost-cell index map along one direction: periodic wrap, or mirror for a
- * reflective wall (the normal velocity of the mirrored cell changes sign). */
+/* Ghost-cell index map along one direction: periodic wrap, mirror for a
+ * reflective wall (the normal velocity of the mirrored cell changes sign), or
+ * the boundary cell itself for a non-reflective boundary (Sec. 5.1, after
+ * Thompson): with every ghost state equal to the boundary cell, the Riemann
+ * problem at the boundary face has no jump, so no wave enters from outside --
+ * the time derivative of each incoming characteristic at the boundary cell
+ * comes from the interior face alone. */
 static int map_index(const orc_problem *pb, int dir, int i, int *flip)
 {
     int n = pb->n[dir];
     if (i < 0) {
         if (pb->bc[dir][0] == 0) return ((i % n) + n) % n;
+        if (pb->bc[dir][0] == 2) return 0;
         *flip = !*flip;
         return -1 - i;
     }
     if (i >= n) {
         if (pb->bc[dir][1] == 0) return i % n;
+        if (pb->bc[dir][1] == 2) return n - 1;
         *flip = !*flip;
         return 2 * n - 1 - i;
     }
     return i;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One-way planar acoustic source (Sec. 2, source-term forcing of the mass,  */
+/* momentum and energy equations on a source plane).                         */
+/*                                                                          */
+/* Written from linear acoustics about the reference liquid state (c0 =      */
+/* sqrt(gamma (p0 + pi_inf) / rho0)): forcing the pressure rate with         */
+/* S_p = c0 A(t) g(s), the momentum along the emission direction n with      */
+/* S_p / c0 and the mass with the isentropic S_p / c0^2 drives only the      */
+/* characteristic p' + rho0 c0 (u'.n), so the plane emits                    */
+/* p' = A(t - s/c0) (smoothed by g) downstream and nothing upstream, and no  */
+/* entropy spot.  s = x - x_s along the axis; g is the normal pdf of         */
+/* standard deviation `width`, cut at 6 widths.  A is a sine burst; its      */
+/* amplitude is raised by exp((k width)^2 / 2), k = 2 pi f / c0, the factor  */
+/* by which the Gaussian's smoothing lowers a sinusoid, so the emitted wave  */
+/* has amplitude src_amp.  The energy forcing is the change of E that S_p,   */
+/* S_m and S_rho make at fixed alpha:                                        */
+/*   S_E = (1 - alpha) S_p / (gamma - 1) + u.S_m - |u|^2 S_rho / 2.          */
+/* ------------------------------------------------------------------------ */
+static double ref_sound_speed(const orc_problem *pb)
+{
+    return sqrt(pb->gamma * (pb->p0 + pb->pi_inf) / pb->rho0);
+}
+
+double orc_source_amplitude(const orc_problem *pb, double t)
+{
+    if (!pb->src_on) return 0.0;
+    double tau = t - pb->src_t0;
+    if (tau < 0.0) return 0.0;
+    if (pb->src_ncyc > 0.0 && tau > pb->src_ncyc / pb->src_freq) return 0.0;
+    double k = 2.0 * ORC_PI * pb->src_freq / ref_sound_speed(pb);
+    return pb->src_amp * exp(0.5 * sq(k * pb->src_width)) * sin(2.0 * ORC_PI * pb->src_freq * tau);
+}
+
+/* Spatial support g at the centre of cell index i along the source axis. */
+static double source_shape(const orc_problem *pb, int i)
+{
+    double s = (i + 0.5) * pb->dx[pb->src_dir] - pb->src_x;
+    double w = pb->src_width;
+    if (fabs(s) > 6.0 * w) return 0.0;
+    return exp(-0.5 * sq(s / w)) / (sqrt(2.0 * ORC_PI) * w);
+}
+
+/* Adds the source at time t to the right-hand side L (nvar entries) of the cell at
+ * coordinates co, whose primitive vector is W. */
+static void acoustic_source(const setup_t *s, const double *W, const int co[3], double t, double *L)
+{
+    const orc_problem *pb = s->pb;
+    double g = source_shape(pb, co[pb->src_dir]);
+    if (g == 0.0) return;
+    double c0 = ref_sound_speed(pb);
+    double Sp = c0 * orc_source_amplitude(pb, t) * g;
+    double Srho = Sp / (c0 * c0);
+    double Sm = pb->src_sign * Sp / c0;
+    double u2 = 0.0;
+    for (int d = 0; d < s->nd; ++d) u2 += sq(W[1 + d]);
+    L[0] += Srho;
+    L[1 + pb->src_dir] += Sm;
+    L[s->iE] += (1.0 - W[s->wA]) * Sp / (pb->gamma - 1.0) + W[1 + pb->src_dir] * Sm - 0.5 * u2 * Srho;
 }
 
 static void gather(const setup_t *s, const double *q, int64_t c, double *qc)
@@ -389,6 +464,58 @@ static void stencil_prim(const setup_t *s, const double *q, int dir, const int c
     if (flip) W[1 + dir] = -W[1 + dir];
 }
 
+/* ------------------------------------------------------------------------ */
+/* Viscous stress of the liquid, eq. stressTensor:                          */
+/*   T = mu (grad u + grad u^T - 2/3 (div u) I),                             */
+/* carried by the momentum flux as -T and by the energy flux as -T.u        */
+/* (eq. euler_transport).  Second-order central differences at the face.    */
+/* ------------------------------------------------------------------------ */
+
+/* Velocity of the cell at co + oa e_a (+ ob e_b when b >= 0), through the ghost-cell map: a mirrored
+ * coordinate negates the velocity component along that direction. */
+static void vel_at(const setup_t *s, const double *q, const int co[3], int a, int oa, int b, int ob, double u[3])
+{
+    const orc_problem *pb = s->pb;
+    int cc[3] = {co[0], co[1], co[2]};
+    int fa = 0, fb = 0;
+    cc[a] = map_index(pb, a, co[a] + oa, &fa);
+    if (b >= 0) cc[b] = map_index(pb, b, co[b] + ob, &fb);
+    int64_t c = lin(pb, cc[0], cc[1], cc[2]);
+    for (int k = 0; k < 3; ++k) u[k] = k < s->nd ? q[(int64_t)(1 + k) * s->N + c] / q[c] : 0.0;
+    if (fa) u[a] = -u[a];
+    if (b >= 0 && fb) u[b] = -u[b];
+}
+
+/* Adds the viscous flux through face co of direction dir (between the cells co - e_dir and co). */
+static void visc_flux(const setup_t *s, const double *q, int dir, const int co[3], double *F)
+{
+    const orc_problem *pb = s->pb;
+    double uL[3], uR[3], g[3][3] = {{0.0}};   /* g[k][e] = d u_k / d x_e at the face */
+    vel_at(s, q, co, dir, -1, -1, 0, uL);
+    vel_at(s, q, co, dir, 0, -1, 0, uR);
+    for (int k = 0; k < s->nd; ++k) g[k][dir] = (uR[k] - uL[k]) / pb->dx[dir];
+    for (int e = 0; e < s->nd; ++e) {
+        if (e == dir) continue;
+        double lp[3], lm[3], rp[3], rm[3];
+        vel_at(s, q, co, dir, -1, e, 1, lp);
+        vel_at(s, q, co, dir, -1, e, -1, lm);
+        vel_at(s, q, co, dir, 0, e, 1, rp);
+        vel_at(s, q, co, dir, 0, e, -1, rm);
+        /* central difference across e in each of the two cells, averaged */
+        for (int k = 0; k < s->nd; ++k)
+            g[k][e] = 0.5 * ((lp[k] - lm[k]) / (2.0 * pb->dx[e]) + (rp[k] - rm[k]) / (2.0 * pb->dx[e]));
+    }
+    double div = 0.0;
+    for (int e = 0; e < s->nd; ++e) div += g[e][e];
+    double work = 0.0;
+    for (int k = 0; k < s->nd; ++k) {
+        double T = pb->mu * (g[dir][k] + g[k][dir] - (k == dir ? 2.0 / 3.0 * div : 0.0));
+        F[1 + k] -= T;
+        work += T * 0.5 * (uL[k] + uR[k]);
+    }
+    F[s->iE] -= work;
+}
+
 static void cell_sources(const setup_t *s, const double *W, const aux_t *ax, double *L)
 {
     const orc_problem *pb = s->pb;
@@ -406,7 +533,7 @@ static void cell_sources(const setup_t *s, const double *W, const aux_t *ax, dou
 /* ------------------------------------------------------------------------ */
 /* Whole-grid right-hand side.                                              */
 /* ------------------------------------------------------------------------ */
-static int rhs_impl(const orc_problem *pb, const double *q, double *rhs, int with_sources)
+static int rhs_impl(const orc_problem *pb, const double *q, double *rhs, int with_sources, double t)
 {
     setup_t s;
     if (setup(pb, &s) != 0) return -1;
@@ -448,6 +575,7 @@ static int rhs_impl(const orc_problem *pb, const double *q, double *rhs, int wit
             }
             double Ff[NVMAX];
             face_flux(&s, dir, Wst, Ff);
+            if (pb->viscous) visc_flux(&s, q, dir, co, Ff);
             for (int v = 0; v < nvar; ++v) F[(int64_t)v * nf + f] = Ff[v];
         }
 #pragma omp parallel for schedule(static)
@@ -466,13 +594,18 @@ static int rhs_impl(const orc_problem *pb, const double *q, double *rhs, int wit
         free(F);
     }
 
-    if (with_sources) {
+    if (with_sources || pb->src_on) {
 #pragma omp parallel for schedule(static)
         for (int64_t c = 0; c < N; ++c) {
             double Wc[NWMAX], Lc[NVMAX];
             for (int k = 0; k < nW; ++k) Wc[k] = W[(int64_t)k * N + c];
             memset(Lc, 0, sizeof(Lc));
-            cell_sources(&s, Wc, &AX[c], Lc);
+            if (with_sources) cell_sources(&s, Wc, &AX[c], Lc);
+            if (pb->src_on) {
+                int co[3] = {(int)(c % pb->n[0]), (int)((c / pb->n[0]) % pb->n[1]),
+                             (int)(c / ((int64_t)pb->n[0] * pb->n[1]))};
+                acoustic_source(&s, Wc, co, t, Lc);
+            }
             for (int v = 0; v < nvar; ++v) rhs[(int64_t)v * N + c] += Lc[v];
         }
     }
@@ -481,9 +614,12 @@ static int rhs_impl(const orc_problem *pb, const double *q, double *rhs, int wit
     return 0;
 }
 
-int orc_rhs(const orc_problem *pb, const double *q, double *rhs) { return rhs_impl(pb, q, rhs, 1); }
+int orc_rhs(const orc_problem *pb, const double *q, double *rhs) { return rhs_impl(pb, q, rhs, 1, pb->t); }
 
-int orc_rhs_flux_only(const orc_problem *pb, const double *q, double *rhs) { return rhs_impl(pb, q, rhs, 0); }
+int orc_rhs_flux_only(const orc_problem *pb, const double *q, double *rhs)
+{
+    return rhs_impl(pb, q, rhs, 0, pb->t);
+}
 
 /* The same right-hand side, one listed cell at a time (stencil primitives are
  * recomputed locally), for spot checks on grids too large for orc_rhs. */
@@ -509,6 +645,12 @@ int orc_rhs_cells(const orc_problem *pb, const double *q, const int64_t *cells, 
             double Fl[NVMAX], Fh[NVMAX];
             face_flux(&s, dir, &Wst[0], Fl);
             face_flux(&s, dir, &Wst[1], Fh);
+            if (pb->viscous) {
+                int hi[3] = {co[0], co[1], co[2]};
+                hi[dir] += 1;
+                visc_flux(&s, q, dir, co, Fl);
+                visc_flux(&s, q, dir, hi, Fh);
+            }
             for (int v = 0; v < nvar; ++v) L[v] += (Fl[v] - Fh[v]) / pb->dx[dir];
         }
         double qc[NVMAX], Wc[NWMAX];
@@ -516,6 +658,7 @@ int orc_rhs_cells(const orc_problem *pb, const double *q, const int64_t *cells, 
         gather(&s, q, c, qc);
         primitives(&s, qc, Wc, &ax);
         cell_sources(&s, Wc, &ax, L);
+        if (pb->src_on) acoustic_source(&s, Wc, co, pb->t, L);
         for (int v = 0; v < nvar; ++v) out[t * nvar + v] = L[v];
     }
     return bad ? -1 : 0;
@@ -616,11 +759,12 @@ static int rk3_flux(const orc_problem *pb, double *q, double dt, int with_source
     double *u2 = (double *)malloc(sizeof(double) * M);
     double *L = (double *)malloc(sizeof(double) * M);
     if (!u1 || !u2 || !L) { free(u1); free(u2); free(L); return -2; }
-    int rc = rhs_impl(pb, q, L, with_sources);
+    /* each stage's L at the time of the state it is evaluated on: u^n at t, u1 at t + dt, u2 at t + dt/2 */
+    int rc = rhs_impl(pb, q, L, with_sources, pb->t);
     for (int64_t m = 0; m < M && rc == 0; ++m) u1[m] = q[m] + dt * L[m];
-    if (rc == 0) rc = rhs_impl(pb, u1, L, with_sources);
+    if (rc == 0) rc = rhs_impl(pb, u1, L, with_sources, pb->t + dt);
     for (int64_t m = 0; m < M && rc == 0; ++m) u2[m] = 0.75 * q[m] + 0.25 * (u1[m] + dt * L[m]);
-    if (rc == 0) rc = rhs_impl(pb, u2, L, with_sources);
+    if (rc == 0) rc = rhs_impl(pb, u2, L, with_sources, pb->t + 0.5 * dt);
     for (int64_t m = 0; m < M && rc == 0; ++m) q[m] = q[m] / 3.0 + 2.0 / 3.0 * (u2[m] + dt * L[m]);
     free(u1);
     free(u2);

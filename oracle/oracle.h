@@ -31,7 +31,7 @@ typedef struct {
     int ndim;            /* 1, 2 or 3 */
     int n[3];            /* cells per direction, unused directions are 1 */
     double dx[3];        /* spacing per direction (m) */
-    int bc[3][2];        /* 0 periodic, 1 reflective, per direction low/high */
+    int bc[3][2];        /* 0 periodic, 1 reflective, 2 non-reflective, per direction low/high */
     double gamma, pi_inf, rho0, p0;   /* stiffened-gas liquid */
     double kappa, sigma, mu, pv;      /* polytropic gas, surface tension, viscosity, vapour */
     int nb;              /* bins (odd) */
@@ -40,6 +40,18 @@ typedef struct {
     int split;           /* 0: sources inside RK3; 1: Strang-split adaptive bubble sub-steps */
     double sub_rtol;     /* relative tolerance of the bubble sub-stepper */
     int max_substeps;
+    int viscous;         /* 1: the liquid's viscous stress (eq. stressTensor) in the mixture fluxes */
+    /* One-way planar acoustic source (Sec. 2, source-term forcing; Sec. 5.1 set-ups). */
+    double t;            /* time of the state handed in (the source waveform's clock) */
+    int src_on;          /* 1: source active */
+    int src_dir;         /* axis of the plane's normal (0, 1, 2) */
+    int src_sign;        /* +1: the wave travels toward +axis, -1: toward -axis */
+    double src_x;        /* plane position along the axis; cell i has its centre at (i + 1/2) dx */
+    double src_width;    /* standard deviation of the Gaussian support (m) */
+    double src_amp;      /* pressure amplitude of the emitted wave (Pa) */
+    double src_freq;     /* frequency (Hz) */
+    double src_t0;       /* start time of the sine */
+    double src_ncyc;     /* cycles emitted (0: continuous) */
 } orc_problem;
 
 /* Bins: ln(R0/R_med) on [-3 sigma, 3 sigma], composite Simpson weights of the
@@ -53,7 +65,7 @@ int orc_init_state(const orc_problem *pb, const double *prim, double *q);
 /* Per-cell diagnostics out[8][N]: n, alpha, M3, M2d, Mp, Mk, p_mix, p_l. */
 int orc_moments(const orc_problem *pb, const double *q, double *out);
 
-/* Right-hand side L(q) of the semi-discrete system (Sec. 3). */
+/* Right-hand side L(q) of the semi-discrete system (Sec. 3), acoustic source at time pb->t. */
 int orc_rhs(const orc_problem *pb, const double *q, double *rhs);
 
 /* L(q) at k listed cells only; out[k][nvar] (cell-major). */
@@ -65,13 +77,17 @@ int orc_rhs_flux_only(const orc_problem *pb, const double *q, double *rhs);
 /* CFL time step: cfl * min over cells and directions of dx_d / (|u_d| + c). */
 double orc_cfl_dt(const orc_problem *pb, const double *q);
 
-/* One SSP-RK3 step in place.  dt <= 0 selects the CFL step.  Returns the step
- * used in *dt_used.  With pb->split = 1 the step is Strang-split. */
+/* One SSP-RK3 step in place from time pb->t (the stages see the source at t, t + dt and
+ * t + dt/2).  dt <= 0 selects the CFL step.  Returns the step used in *dt_used.  With
+ * pb->split = 1 the step is Strang-split. */
 int orc_rk3_step(const orc_problem *pb, double *q, double dt, double *dt_used);
 
 /* Adaptive bubble half-step of split mode on the whole grid (exposed for tests).
  * nsub_out (may be NULL) receives per-(cell,bin) accepted sub-step counts [nb][N]. */
 int orc_bubble_advance(const orc_problem *pb, double *q, double dt, int32_t *nsub_out);
+
+/* Pressure amplitude A(t) the acoustic source emits at time t (0 outside its burst). */
+double orc_source_amplitude(const orc_problem *pb, double t);
 
 /* OpenMP threads used by the parallel loops (1 without OpenMP). */
 int orc_num_threads(void);

@@ -29,6 +29,12 @@ Workloads (water as a stiffened gas, air bubbles, polytropic contents):
   (N uniform in 200..4000), 25 % 2D (side 64..512), 5 % 3D 96^3; bins in
   {11, 21, 31}; alpha log-uniform in [1e-5, 1e-3]; amplitude 0.1..5 atm;
   50..500 steps.
+* ``acoustic_tube`` / ``pulse_tube``  the validation set-ups of the one-way
+  acoustic source and the non-reflective boundaries: water at rest in a tube
+  with non-reflective ends, either driven by a planar sine burst of 50 cells
+  per wavelength emitted from the middle, or carrying a right-running
+  Gaussian pulse (p' = P exp(-((x - x0)/w)^2), u' = p'/(rho0 c0),
+  rho' = p'/c0^2) toward the right end.
 
 Every size can be shrunk by argument so that tests run the same recipe on
 grids the CPU oracle finishes in seconds.
@@ -49,6 +55,7 @@ AIR = dict(kappa=1.4, sigma=0.0728, mu=1.0e-3, pv=0.0)
 # Boundary codes shared by both sides' problem descriptions.
 BC_PERIODIC = 0
 BC_REFLECTIVE = 1
+BC_NONREFLECTIVE = 2
 
 
 def c0_water() -> float:
@@ -303,3 +310,43 @@ def request_case(r: Request) -> Case:
     prim = _pack([rho] + [z0] * r.ndim + [p, a], nn)
     rb = ((BC_REFLECTIVE, BC_REFLECTIVE),) * 3
     return Case(f"req{r.rid}", r.ndim, nn, (r.dx, r.dx, r.dx), rb, r.nb, 10e-6, 0.3, 0.3, r.steps, prim)
+
+
+# ---------------------------------------------------------------------------
+# Acoustic source and non-reflective boundary set-ups
+# ---------------------------------------------------------------------------
+
+def source_burst(axis: int, sign: int, x: float, dx: float, *, cells_per_wavelength: float = 50.0,
+                 width_cells: float = 3.0, amp: float = 1e3, cycles: float = 3.0, t0: float = 0.0) -> dict:
+    """Parameters of a planar sine burst (frequency from the wavelength in cells at the water sound speed)."""
+    f = c0_water() / (cells_per_wavelength * dx)
+    return dict(dir=axis, sign=sign, x=x, width=width_cells * dx, amp=amp, freq=f, t0=t0, ncyc=cycles)
+
+
+def acoustic_tube(ndim: int = 1, n: int = 600, length: float = 0.15, nb: int = 1, *, alpha: float = 0.0,
+                  axis: int = 0, ncross: int = 4, bc=BC_NONREFLECTIVE, cfl: float = 0.3) -> Case:
+    """Water at rest with the given void fraction; `n` cells of length/n along `axis`, `ncross` periodic
+    cells across it (2D and 3D); non-reflective ends along the axis."""
+    dx = length / n
+    nn = [1, 1, 1]
+    for d in range(ndim):
+        nn[d] = n if d == axis else ncross
+    nn = tuple(nn)
+    w = WATER
+    fields = [np.full((1, 1, 1), w["rho0"])] + [np.zeros((1, 1, 1))] * ndim \
+        + [np.full((1, 1, 1), w["p0"]), np.full((1, 1, 1), alpha)]
+    bcs = tuple((bc, bc) if d == axis else (BC_PERIODIC, BC_PERIODIC) for d in range(3))
+    return Case("acoustic_tube", ndim, nn, (dx, dx, dx), bcs, nb, 10e-6, 0.3, cfl, 1, _pack(fields, nn))
+
+
+def pulse_tube(n: int = 400, length: float = 0.1, *, amp: float = 1e3, x0_frac: float = 0.6,
+               width_cells: float = 12.0, nb: int = 1, alpha: float = 0.0, bc=BC_NONREFLECTIVE) -> Case:
+    """1D water tube carrying a right-running Gaussian acoustic pulse (linear acoustics initial data)."""
+    dx = length / n
+    x = _centres(n, dx)
+    c0 = c0_water()
+    w = WATER
+    pp = amp * np.exp(-((x - x0_frac * length) / (width_cells * dx)) ** 2)
+    prim = np.stack([w["rho0"] + pp / c0 ** 2, pp / (w["rho0"] * c0), w["p0"] + pp, np.full(n, alpha)])
+    return Case("pulse_tube", 1, (n, 1, 1), (dx, 1.0, 1.0), ((bc, bc), (BC_PERIODIC, BC_PERIODIC),
+                (BC_PERIODIC, BC_PERIODIC)), nb, 10e-6, 0.3, 0.3, 1, prim)
