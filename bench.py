@@ -133,13 +133,14 @@ def serving(args):
 
     # warm-up: code objects of every dimensionality and both precisions, on tiny solves
     warm = workloads.c5_stream(count=12, seed=5, scale=0.05)
-    Server(1 << 34, max_slots=8, chunk=2).run(warm, workloads.request_case, time_scale=0.0)
+    use_run = args.batch_mode == "run"
+    Server(1 << 34, max_slots=8, chunk=2, use_run=use_run).run(warm, workloads.request_case, time_scale=0.0)
     run_sequential(warm[:3], workloads.request_case, bub.PREC_FP64, bub.BUBBLES_SPLIT, time_scale=0.0)
     torch.cuda.synchronize()
 
     budget = int(args.budget_gib * (1 << 30))
     srv = Server(budget, max_slots=args.slots, precision=bub.PREC_MIXED, bubble_mode=bub.BUBBLES_SPLIT, chunk=10,
-                 lanes=args.lanes)
+                 lanes=args.lanes, use_run=use_run)
     ts = 0.0 if args.burst else 1.0
     recs = srv.run(reqs, workloads.request_case, time_scale=ts, progress=progress("served"))
     t_srv = max(r.finished for r in recs)
@@ -162,7 +163,8 @@ def serving(args):
                                + ("all arriving at t=0" if args.burst else f"Poisson arrivals at {args.rate}/s")
                                + f" (70% 1D 200-4000 cells, 25% 2D 64^2-512^2, 5% 3D 96^3; 11/21/31 "
                                f"bins; 50-500 steps), split bubble sub-stepping, mixed precision",
-                   "hbm_budget_gib": args.budget_gib, "max_slots": args.slots, "chunk": 10, "lanes": args.lanes,
+                   "hbm_budget_gib": args.budget_gib, "max_slots": args.slots, "chunk": 10,
+                   "batch_mode": args.batch_mode, "lanes": args.lanes,
                    "hw_queues": args.hw_queues or "HIP default",
                    "cell_bin_rk_steps": cell_bin_steps},
         "serving": {"p50_s": s_srv["p50_s"], "p99_s": s_srv["p99_s"], "mean_s": s_srv["mean_s"],
@@ -275,7 +277,9 @@ def main():
     ap.add_argument("--slots", type=int, default=64, help="serving: batch slots (resident problems at most)")
     ap.add_argument("--no-sequential", action="store_true", help="serving: skip the sequential FP64 baseline")
     ap.add_argument("--burst", action="store_true", help="serving: every request arrives at t = 0")
-    ap.add_argument("--lanes", type=int, default=4, help="serving: batch streams")
+    ap.add_argument("--lanes", type=int, default=4, help="serving: batch streams (lanes mode)")
+    ap.add_argument("--batch-mode", choices=["run", "step"], default="run",
+                    help="serving: chunks through bub_batch_run (step counts, completion flags) or bub_batch_step")
     ap.add_argument("--hw-queues", type=int, default=0,
                     help="serving: hardware queues per process (HIP GPU_MAX_HW_QUEUES, at most 32; 0 = HIP default)")
     args = ap.parse_args()

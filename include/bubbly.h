@@ -80,8 +80,18 @@ typedef struct { int nb; double r0_median, sigma_ln; } bub_bins;
  * FP64 primitives, moments, Keller--Miksis, sources and RK accumulation).
  * bubble_mode: BUB_BUBBLES_UNSPLIT (bubble sources inside every RK stage) or
  * BUB_BUBBLES_SPLIT (Strang splitting with adaptive embedded RK3/RK2 bubble
- * sub-steps, Sec. 3; sub_rtol and max_substeps apply). */
-typedef struct { double cfl; int precision; int bubble_mode; double sub_rtol; int max_substeps; } bub_opts;
+ * sub-steps, Sec. 3; sub_rtol and max_substeps apply).  viscous: 0 for an
+ * inviscid carrier (the liquid viscosity gas.mu enters Keller--Miksis only), 1
+ * to add the liquid's viscous stress T = mu (grad u + grad u^T - 2/3 div(u) I)
+ * (eq. stressTensor) to the mixture fluxes: -T in the momentum flux and -T.u in
+ * the energy flux of eq. euler_transport, by second-order central differences
+ * at each face (normal derivatives from the two cells, transverse derivatives
+ * averaged over the two cells' central differences, face velocity their mean).
+ * The stress is added by a pass after each stage kernel (so the stages of a
+ * viscous problem take a separate primitive pass).  The time step stays the
+ * acoustic CFL step (the viscous limit dx^2/(2 ndim nu) is far larger at
+ * bubbly-flow scales). */
+typedef struct { double cfl; int precision; int bubble_mode; double sub_rtol; int max_substeps; int viscous; } bub_opts;
 
 typedef struct bub_ctx bub_ctx;
 
@@ -227,34 +237,69 @@ int bub_lagrangian_step(bub_ctx *ctx, double *ql, double *bubbles, int64_t nbub,
 /* ---- Batches: many resident problems advanced together ----
  * A batch holds up to max_cases problems (contexts of any dimensionality, bin
  * count, size and bubble mode, all of the batch's precision) with their state q
- * and work buffer (caller-owned device memory, as for bub_rk3_step).
- * bub_batch_step advances every member by nsteps CFL-limited SSP-RK3 steps
- * (each member its own step size).  The members are dealt, largest first, over
- * a few internal streams (default priority) so that the kernels of small
- * problems overlap on the device; the internal streams start after the work
- * already queued on `stream`, and `stream` continues only after all of them,
- * so to the caller the call is one stream-ordered operation.  Each member runs
- * exactly the kernels of bub_rk3_step on its own buffers: its result is
- * bitwise the same as bub_rk3_step alone, whatever the other members are.
+ * and work buffer (caller-owned device memory, as for bub_rk3_step).  Every
+ * step of a member is a CFL-limited SSP-RK3 step with its own step size, and a
+ * member's result is bitwise the one bub_rk3_step gives it alone, whatever the
+ * other members are.  Two ways to advance the members:
+ *
+ *  * bub_batch_run: a chunk of steps for the members that still have steps to
+ *    take.  Members are added with the number of steps they need; completion is
+ *    reported by bub_batch_poll from flags in pinned host memory.  The chunk is
+ *    stepped as in the lanes form.  (The library also holds a grouped form of
+ *    the chunk -- every phase of a step one kernel launch per kernel class over
+ *    a device table of the members -- which is switched off in this build: on
+ *    the GPU it has corrupted member states, for a cause not yet found.)
+ *  * bub_batch_step (lanes): each member's bub_rk3_step, dealt largest first
+ *    over a few internal streams (default priority) so that small problems'
+ *    kernels overlap.
+ *
  * Members keep their own error word (bub_last_error or bub_error_copy on the
- * member's context).  A context may be in one batch slot at a time and must
- * not be destroyed, nor its buffers freed, while it is a member or while a
- * step that included it may still be running.  Not thread-safe. */
+ * member's context).  A context may be in one batch slot at a time and must not
+ * be destroyed, nor its buffers freed, while it is a member or while a step
+ * that included it may still be running.  All calls on one batch must be made
+ * from one thread with one stream.  This replaces the void* batch of a plain
+ * pointer-and-size interface; the call names and roles are kept. */
 typedef struct bub_batch bub_batch;
 
-/* BUB_EHIP if the internal streams or events cannot be created. */
-int bub_batch_create(int precision, int max_cases, bub_batch **out);
-/* Waits for the internal streams, then releases them. */
+/* hbm_budget: device bytes the members may hold together (state, work and the
+ * context's buffers of each; 0 = no budget); bub_batch_add refuses a member
+ * that does not fit.  max_cases in 1..256.  BUB_ENOMEM if the batch's device
+ * table or its pinned flags cannot be allocated, BUB_EHIP if its internal
+ * streams or events cannot be created. */
+int bub_batch_create(int precision, int max_cases, size_t hbm_budget, bub_batch **out);
+/* Waits for the device, then releases the batch's streams, graphs, table and flags. */
 int bub_batch_destroy(bub_batch *batch);
 
-/* Add a member; *slot receives its handle.  BUB_EINVAL if the batch is full,
- * the precision differs, the context is already a member, or q and work
- * overlap.  A member whose (ndim, nb) class was autotuned gets that class's
- * stage tile shape. */
-int bub_batch_add(bub_batch *batch, bub_ctx *ctx, double *q, double *work, int *slot);
+/* Add a member that needs `steps` more steps from bub_batch_run (0: open-ended,
+ * stepped by every run and never reported done); *slot receives its handle.
+ * BUB_ENOMEM if its bytes (3 state copies + bub_ctx_buffer_bytes) exceed what
+ * the budget has left; BUB_EINVAL if the batch is full, steps < 0, the precision
+ * differs, the context is already a member, or q and work overlap;
+ * BUB_EUNSUPPORTED for a viscous context (opts.viscous = 1).  A member whose
+ * (ndim, nb) class was autotuned gets that class's stage tile shape. */
+int bub_batch_add(bub_batch *batch, bub_ctx *ctx, double *q, double *work, int steps, int *slot);
+/* Remove a member (its bytes return to the budget).  Its buffers must stay
+ * valid until the work already enqueued for it has finished. */
 int bub_batch_remove(bub_batch *batch, int slot);
 
-/* nsteps steps of every member, ordered on `stream` (no host synchronisation). */
+/* Advance every member that still has steps to take (and every open-ended
+ * one) by n = min(max_steps, fewest steps left among them) steps, ordered on
+ * `stream` (no host synchronisation; the members' steps run on the batch's
+ * lanes between a fork from and a join back into `stream`).  *steps_taken (may
+ * be NULL) receives n (0 when nothing is left).  Members that reach their last
+ * step get a completion flag written on `stream` after the chunk. */
+int bub_batch_run(bub_batch *batch, int max_steps, int *steps_taken, void *stream);
+/* Slots whose last step has completed on the device since the last poll
+ * (read from the pinned flags, no synchronisation).  done_slots: host array of
+ * max_cases entries; *ndone receives how many were written.  A reported member
+ * stays in its slot until removed and is not stepped again. */
+int bub_batch_poll(bub_batch *batch, int *done_slots, int *ndone);
+/* Steps a member still has to take in bub_batch_run (-1 for an open-ended one). */
+int bub_batch_remaining(const bub_batch *batch, int slot, int *steps);
+
+/* Lanes form: nsteps steps of every member, ordered on `stream` (no host
+ * synchronisation).  The internal streams start after the work already queued
+ * on `stream`, and `stream` continues only after all of them. */
 int bub_batch_step(bub_batch *batch, int nsteps, void *stream);
 
 /* Number of internal streams ("lanes", 1..16, default 4) the members are dealt
@@ -263,12 +308,12 @@ int bub_batch_step(bub_batch *batch, int nsteps, void *stream);
  * lanes pay only with more queues.  BUB_EINVAL outside 1..16. */
 int bub_batch_lanes(bub_batch *batch, int lanes);
 
-/* Graph mode (on by default): each member's step is captured once as a HIP
- * graph (its kernels only) and replayed with one graph launch per step, which
- * cuts the host's launch work about tenfold; a member is captured again when
- * its tile shape or bin grouping changes, and profiled members launch
- * directly.  enable = 0 launches every kernel directly.  Results are the same
- * either way. */
+/* Graph mode (on by default).  Lanes form: each member's step is captured once
+ * as a HIP graph (its kernels only) and replayed with one graph launch per
+ * step, which cuts the host's launch work about tenfold; a member is captured
+ * again when its tile shape or bin grouping changes, and profiled members
+ * launch directly.  enable = 0 launches every kernel directly.  Results are
+ * the same either way. */
 int bub_batch_graphs(bub_batch *batch, int enable);
 
 /* Members, total cells and total cell-bins of the current members. */

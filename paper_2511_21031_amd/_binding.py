@@ -42,7 +42,7 @@ class _Bins(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("cfl", ctypes.c_double), ("precision", ctypes.c_int), ("bubble_mode", ctypes.c_int),
-                ("sub_rtol", ctypes.c_double), ("max_substeps", ctypes.c_int)]
+                ("sub_rtol", ctypes.c_double), ("max_substeps", ctypes.c_int), ("viscous", ctypes.c_int)]
 
 
 _lib = None
@@ -85,9 +85,12 @@ _SIGS = {
     "bub_bin_groups": [_vp, ctypes.c_int],
     "bub_substep_counts": [_vp, _vp],
     "bub_autotune": [_vp, _vp, _vp, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int), _vp],
-    "bub_batch_create": [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)],
+    "bub_batch_create": [ctypes.c_int, ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_vp)],
     "bub_batch_destroy": [_vp],
-    "bub_batch_add": [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_int)],
+    "bub_batch_add": [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
+    "bub_batch_run": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _vp],
+    "bub_batch_poll": [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
+    "bub_batch_remaining": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
     "bub_batch_remove": [_vp, ctypes.c_int],
     "bub_batch_step": [_vp, ctypes.c_int, _vp],
     "bub_batch_info": [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
@@ -146,7 +149,7 @@ class Context:
 
     def __init__(self, ndim, n, dx, bc, nb, r0_median=10e-6, sigma_ln=0.3, liquid=None, gas=None, cfl=0.3,
                  precision=PREC_FP64, bubble_mode=BUBBLES_UNSPLIT, sub_rtol=1e-4, max_substeps=10000,
-                 torch_buffer=False, stream=None):
+                 torch_buffer=False, stream=None, viscous=0):
         """torch_buffer=True: the context's device memory is a torch tensor and it is initialised on
         `stream` (bub_ctx_create_on): no allocation call and no host synchronisation."""
         L = lib()
@@ -162,7 +165,7 @@ class Context:
         lq = _Liquid(liquid["gamma"], liquid["pi_inf"], liquid["rho0"], liquid["p0"])
         gs = _Gas(gas["kappa"], gas["sigma"], gas["mu"], gas["pv"])
         bn = _Bins(nb, r0_median, sigma_ln)
-        op = _Opts(cfl, precision, bubble_mode, sub_rtol, max_substeps)
+        op = _Opts(cfl, precision, bubble_mode, sub_rtol, max_substeps, int(viscous))
         h = _vp()
         self._buf = None
         if torch_buffer:
@@ -388,14 +391,17 @@ def ctx_buffer_bytes(ndim, n, nb) -> int:
 
 
 class Batch:
-    """Resident problems advanced together (bub_batch_*): one call steps every member, the members'
-    kernels overlapping on the device over the batch's internal streams."""
+    """Resident problems advanced together (bub_batch_*).  run(): a chunk of steps for the members that
+    still have steps to take, completion read by poll(); step(): every member's steps.  Both step each
+    member with its own kernels, overlapping over the batch's internal streams."""
 
-    def __init__(self, precision=PREC_FP64, max_cases=64):
+    def __init__(self, precision=PREC_FP64, max_cases=64, hbm_budget=0):
         h = _vp()
-        _check(lib().bub_batch_create(int(precision), int(max_cases), ctypes.byref(h)), "bub_batch_create")
+        _check(lib().bub_batch_create(int(precision), int(max_cases), int(hbm_budget), ctypes.byref(h)),
+               "bub_batch_create")
         self._h = h
         self.precision = precision
+        self.max_cases = int(max_cases)
         self._members = {}     # slot -> (ctx, q, work): keeps buffers alive while resident
 
     def close(self):
@@ -410,13 +416,34 @@ class Batch:
         except Exception:
             pass
 
-    def add(self, ctx: Context, q: torch.Tensor, work: torch.Tensor) -> int:
+    def add(self, ctx: Context, q: torch.Tensor, work: torch.Tensor, steps: int = 0) -> int:
+        """Add a member needing `steps` steps from run() (0: open-ended); returns its slot."""
         if q.numel() * 8 < ctx.state_bytes or work.numel() * 8 < ctx.work_bytes:
             raise ValueError("state or work buffer too small")
         slot = ctypes.c_int()
-        _check(lib().bub_batch_add(self._h, ctx._h, _ptr(q), _ptr(work), ctypes.byref(slot)), "bub_batch_add")
+        _check(lib().bub_batch_add(self._h, ctx._h, _ptr(q), _ptr(work), int(steps), ctypes.byref(slot)),
+               "bub_batch_add")
         self._members[slot.value] = (ctx, q, work)
         return slot.value
+
+    def run(self, max_steps: int, stream=None) -> int:
+        """Grouped chunk of at most max_steps steps (never past the member with the fewest left);
+        returns the steps taken."""
+        n = ctypes.c_int()
+        _check(lib().bub_batch_run(self._h, int(max_steps), ctypes.byref(n), _stream(stream)), "bub_batch_run")
+        return n.value
+
+    def poll(self):
+        """Slots whose last step has completed on the device since the last poll (no synchronisation)."""
+        buf = (ctypes.c_int * self.max_cases)()
+        n = ctypes.c_int()
+        _check(lib().bub_batch_poll(self._h, buf, ctypes.byref(n)), "bub_batch_poll")
+        return [buf[i] for i in range(n.value)]
+
+    def remaining(self, slot: int) -> int:
+        v = ctypes.c_int()
+        _check(lib().bub_batch_remaining(self._h, int(slot), ctypes.byref(v)), "bub_batch_remaining")
+        return v.value
 
     def remove(self, slot: int):
         _check(lib().bub_batch_remove(self._h, int(slot)), "bub_batch_remove")

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 
@@ -15,6 +16,9 @@
 #include "split_kernels.hpp"
 #include "stage_kernel.hpp"
 #include "el_kernels.hpp"
+#include "batch_kernels.hpp"
+#include "batch_plan.hpp"
+#include "viscous_kernel.hpp"
 
 #include <vector>
 #include "ctx.hpp"
@@ -241,7 +245,7 @@ int prim(bub_ctx *c, const double *q, double *out, int mode, hipStream_t s)
     }
 }
 
-int stage(bub_ctx *c, const StageArgs &A, hipStream_t s)
+int stage_kernel(bub_ctx *c, const StageArgs &A, hipStream_t s)
 {
     const int v = c->tile;
     switch (c->ndim) {
@@ -265,6 +269,24 @@ int stage(bub_ctx *c, const StageArgs &A, hipStream_t s)
     }
 }
 
+// An RK stage (or a right-hand side): the stage kernel, then, for a viscous problem, the viscous
+// pass that adds the stress of eq. stressTensor to the momentum and energy the kernel wrote.
+int stage(bub_ctx *c, const StageArgs &A, hipStream_t s)
+{
+    int rc = stage_kernel(c, A, s);
+    if (rc || !c->opts.viscous || !(c->gas.mu > 0.0)) return rc;
+    long pr = prof_begin(c, BUB_K_OTHER, s);
+    const dim3 grid(blocks_for(c->N)), block(256);
+    const double *dtp = A.rhs_mode ? nullptr : A.dtp;
+    switch (c->ndim) {
+    case 1: hipLaunchKernelGGL((k_viscous<1>), grid, block, 0, s, A.P, A.qo, c->g, c->gas.mu, dtp, A.b); break;
+    case 2: hipLaunchKernelGGL((k_viscous<2>), grid, block, 0, s, A.P, A.qo, c->g, c->gas.mu, dtp, A.b); break;
+    default: hipLaunchKernelGGL((k_viscous<3>), grid, block, 0, s, A.P, A.qo, c->g, c->gas.mu, dtp, A.b); break;
+    }
+    prof_end(c, pr, s);
+    return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
+}
+
 // Tiles of the context's current stage shape.
 long long stage_tiles(const bub_ctx *c)
 {
@@ -278,7 +300,8 @@ long long stage_tiles(const bub_ctx *c)
 // one thread per cell (then both forms sum the bins in the same order, so results are bitwise equal).
 bool stage_fusable(const bub_ctx *c)
 {
-    if (!c->d_P2 || slots_for(c->N) != 1) return false;
+    // (a viscous pass after the stage changes the state the epilogue would describe)
+    if (!c->d_P2 || slots_for(c->N) != 1 || c->opts.viscous) return false;
     int groups = 0;
     bin_grouping(c, stage_tiles(c), &groups);
     return groups == 1;
@@ -388,6 +411,7 @@ int ctx_fill(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, co
     if (opts->bubble_mode != BUB_BUBBLES_UNSPLIT && opts->bubble_mode != BUB_BUBBLES_SPLIT) return BUB_EINVAL;
     if (opts->bubble_mode == BUB_BUBBLES_SPLIT && (!(opts->sub_rtol > 0.0) || opts->max_substeps < 1))
         return BUB_EINVAL;
+    if (opts->viscous != 0 && opts->viscous != 1) return BUB_EINVAL;
 
     c->grid = *grid;
     c->liq = *liq;
@@ -1072,7 +1096,35 @@ struct bub_batch {
         bool used = false;
         hipGraphExec_t exec = nullptr;   // one captured rk3_step of this member (graph mode)
         int cap_tile = -1, cap_groups = -1;
+        size_t bytes = 0;                // device bytes counted against the budget
+        int remaining = 0;               // steps still to take in bub_batch_run (0 with open = false: finished)
+        bool open = false;               // added with steps = 0: stepped by every run, never finished
+        int done_epoch = 0;              // epoch of the flag that marks its last step done (0: none)
+        bool reported = false;           // bub_batch_poll has returned it
     };
+    // grouped launches (bub_batch_run)
+    size_t budget = 0, used_bytes = 0;            // device bytes of the members; budget 0 = none
+    BatchMember *d_tab = nullptr;                 // device member table [max_cases]
+    LaunchList *d_lists = nullptr;                // device launch lists [NLISTS]
+    static constexpr int NLISTS = 48;
+    int *h_flags = nullptr, *d_flags = nullptr;   // completion flags in pinned host memory [max_cases]
+    // table and list uploads: a ring of pinned staging buffers, each reused only after the event
+    // recorded behind its last upload has completed
+    static constexpr int NSTAGE = 8;
+    char *h_stage[NSTAGE] = {};
+    hipEvent_t stage_ev[NSTAGE] = {};
+    bool stage_used[NSTAGE] = {};
+    int stage_next = 0;
+    int epoch = 0;
+    bool dirty = true;                            // table or lists out of date
+    int version = 0;                              // bumped whenever they are rewritten
+    struct Launch { int d, key, list; long long blocks; };   // key: slots (prim/bubble) or tile (stage)
+    std::vector<Launch> prim_all, prim_split, stage_l;
+    int dt_list = -1, dt_count = 0;
+    hipGraphExec_t run_exec = nullptr;            // captured chunk of grouped launches
+    hipEvent_t run_ev = nullptr;                  // recorded after every launch of run_exec
+    int run_steps = -1, run_version = -1;
+    std::vector<std::pair<hipGraphExec_t, hipEvent_t>> run_retired;   // freed once their event completed
     int precision = 0;
     bool graphs = true;                           // replay each member's step as one captured graph
     hipStream_t cap = nullptr;                    // capture stream (never executes work)
@@ -1088,6 +1140,17 @@ struct bub_batch {
 };
 
 namespace {
+
+// Whether p lies in device memory of the current HIP runtime (host memory, pinned or not, does not).
+bool is_device_memory(const void *p)
+{
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice;
+}
 
 int batch_class_tile(const bub_batch *b, const bub_ctx *c)
 {
@@ -1135,13 +1198,37 @@ int batch_free_retired(bub_batch *b)
 
 extern "C" {
 
-int bub_batch_create(int precision, int max_cases, bub_batch **out)
+int bub_batch_create(int precision, int max_cases, size_t hbm_budget, bub_batch **out)
 {
-    if (!out || max_cases < 1 || (precision != BUB_PREC_FP64 && precision != BUB_PREC_MIXED)) return BUB_EINVAL;
+    if (!out || max_cases < 1 || max_cases > BATCH_MAX || (precision != BUB_PREC_FP64 && precision != BUB_PREC_MIXED))
+        return BUB_EINVAL;
     bub_batch *b = new (std::nothrow) bub_batch();
     if (!b) return BUB_ENOMEM;
     b->precision = precision;
+    b->budget = hbm_budget;
     b->slots.resize(max_cases);
+    if (hipMalloc(&b->d_tab, sizeof(BatchMember) * (size_t)max_cases) != hipSuccess ||
+        hipMalloc(&b->d_lists, sizeof(LaunchList) * (size_t)bub_batch::NLISTS) != hipSuccess ||
+        hipHostMalloc(&b->h_flags, sizeof(int) * (size_t)max_cases, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        bub_batch_destroy(b);
+        return BUB_ENOMEM;
+    }
+    std::memset(b->h_flags, 0, sizeof(int) * (size_t)max_cases);
+    const size_t stage_bytes = sizeof(BatchMember) * (size_t)max_cases + sizeof(LaunchList) * bub_batch::NLISTS;
+    for (int k = 0; k < bub_batch::NSTAGE; ++k) {
+        if (hipHostMalloc((void **)&b->h_stage[k], stage_bytes, hipHostMallocDefault) != hipSuccess) {
+            bub_batch_destroy(b);
+            return BUB_ENOMEM;
+        }
+        if (hipEventCreateWithFlags(&b->stage_ev[k], hipEventDisableTiming) != hipSuccess) {
+            bub_batch_destroy(b);
+            return BUB_EHIP;
+        }
+    }
+    if (hipHostGetDevicePointer((void **)&b->d_flags, b->h_flags, 0) != hipSuccess) {
+        bub_batch_destroy(b);
+        return BUB_EHIP;
+    }
     bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess &&
               hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess;
     for (int k = 0; k < bub_batch::NSTREAM && ok; ++k)
@@ -1167,27 +1254,57 @@ int bub_batch_destroy(bub_batch *b)
     }
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->d_tab || b->d_lists || b->h_flags || b->h_stage[0]) (void)hipDeviceSynchronize();   // work may still use them
+    if (b->run_exec) (void)hipGraphExecDestroy(b->run_exec);
+    if (b->run_ev) (void)hipEventDestroy(b->run_ev);
+    for (auto &r : b->run_retired) {
+        (void)hipGraphExecDestroy(r.first);
+        (void)hipEventDestroy(r.second);
+    }
+    if (b->d_tab) (void)hipFree(b->d_tab);
+    if (b->d_lists) (void)hipFree(b->d_lists);
+    if (b->h_flags) (void)hipHostFree(b->h_flags);
+    for (int k = 0; k < bub_batch::NSTAGE; ++k) {
+        if (b->h_stage[k]) (void)hipHostFree(b->h_stage[k]);
+        if (b->stage_ev[k]) (void)hipEventDestroy(b->stage_ev[k]);
+    }
     delete b;
     return BUB_OK;
 }
 
-int bub_batch_add(bub_batch *b, bub_ctx *c, double *q, double *work, int *slot)
+int bub_batch_add(bub_batch *b, bub_ctx *c, double *q, double *work, int steps, int *slot)
 {
-    if (!b || !c || !q || !work || !slot) return BUB_EINVAL;
+    if (!b || !c || !q || !work || !slot || steps < 0) return BUB_EINVAL;
     if (c->opts.precision != b->precision) return BUB_EINVAL;
+    if (c->opts.viscous) return BUB_EUNSUPPORTED;   // the grouped launches carry no viscous pass
     const size_t M = (size_t)c->nvar * (size_t)c->N;
     if ((q >= work && q < work + 2 * M) || (work >= q && work < q + M)) return BUB_EINVAL;
     for (size_t i = 0; i < b->slots.size(); ++i) {
         auto &m = b->slots[i];
         if (m.used && m.ctx == c) return BUB_EINVAL;
     }
+    // every pointer the grouped kernels will read from the member table must be device memory
+    if (!is_device_memory(q) || !is_device_memory(work) || !is_device_memory(c->d_P) ||
+        !is_device_memory(c->d_sc) || !is_device_memory(c->d_bins))
+        return BUB_EINVAL;
+    size_t off_sc, off_P, off_P2, ctx_bytes;
+    ctx_buffer_layout(c->ndim, c->N, &off_sc, &off_P, &off_P2, &ctx_bytes);
+    const size_t bytes = 3 * sizeof(double) * M + ctx_bytes;   // state, work, the context's buffers
+    if (b->budget && b->used_bytes + bytes > b->budget) return BUB_ENOMEM;
     for (size_t i = 0; i < b->slots.size(); ++i) {
         auto &m = b->slots[i];
         if (!m.used) {
+            m = bub_batch::Member{};
             m.ctx = c;
             m.q = q;
             m.work = work;
             m.used = true;
+            m.bytes = bytes;
+            m.remaining = steps;
+            m.open = steps == 0;
+            b->used_bytes += bytes;
+            b->h_flags[i] = 0;
+            b->dirty = true;
             const int t = batch_class_tile(b, c);
             if (t >= 0) c->tile = t;
             *slot = (int)i;
@@ -1201,7 +1318,9 @@ int bub_batch_remove(bub_batch *b, int slot)
 {
     if (!b || slot < 0 || slot >= (int)b->slots.size() || !b->slots[slot].used) return BUB_EINVAL;
     if (b->slots[slot].exec) b->retired.push_back(b->slots[slot].exec);   // launches may still be in flight
+    b->used_bytes -= b->slots[slot].bytes;
     b->slots[slot] = bub_batch::Member{};
+    b->dirty = true;
     return BUB_OK;
 }
 
@@ -1222,14 +1341,19 @@ int bub_batch_info(const bub_batch *b, int *ncases, int64_t *cells, int64_t *cel
     return BUB_OK;
 }
 
-int bub_batch_step(bub_batch *b, int nsteps, void *stream)
+}  // extern "C"
+
+namespace {
+
+// nsteps steps of the members that `pick` selects, each member's own step kernels (or its captured
+// step graph) on one of the batch's lanes, forked from and joined back into the caller's stream.
+template <typename Pick>
+int lanes_steps(bub_batch *b, int nsteps, hipStream_t s, Pick pick)
 {
-    if (!b || nsteps < 0) return BUB_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
     // members, largest first, dealt to the least-loaded stream (work ~ cells x variables)
     std::vector<int> order;
     for (size_t i = 0; i < b->slots.size(); ++i)
-        if (b->slots[i].used) order.push_back((int)i);
+        if (pick(b->slots[i])) order.push_back((int)i);
     if (order.empty() || nsteps == 0) return BUB_OK;
     auto work_of = [&](int i) { return (double)b->slots[i].ctx->N * (double)b->slots[i].ctx->nvar; };
     std::sort(order.begin(), order.end(), [&](int x, int y) { return work_of(x) > work_of(y); });
@@ -1278,6 +1402,16 @@ int bub_batch_step(bub_batch *b, int nsteps, void *stream)
     return BUB_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int bub_batch_step(bub_batch *b, int nsteps, void *stream)
+{
+    if (!b || nsteps < 0) return BUB_EINVAL;
+    return lanes_steps(b, nsteps, (hipStream_t)stream, [](const bub_batch::Member &m) { return m.used; });
+}
+
 int bub_batch_graphs(bub_batch *b, int enable)
 {
     if (!b) return BUB_EINVAL;
@@ -1311,6 +1445,7 @@ int bub_batch_autotune(bub_batch *b, int reps, int *classes, void *stream)
         }
         m.ctx->tile = t;
     }
+    b->dirty = true;   // stage decompositions of the grouped launches follow the tiles
     if (classes) *classes = (int)b->tuned_key.size();
     (void)tuned;
     return BUB_OK;
@@ -1318,3 +1453,319 @@ int bub_batch_autotune(bub_batch *b, int reps, int *classes, void *stream)
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------
+// Batches, grouped form: one launch per phase and kernel class over a device member table
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int PRIM_CELLS_1 = 256, PRIM_CELLS_S = 64;   // cells per primitive/bubble block (as launch_prim)
+
+int cells_for(int S) { return S == 1 ? PRIM_CELLS_1 : PRIM_CELLS_S; }
+
+// The member's view for the grouped kernels; the stage decomposition is the one its own launch uses.
+int member_desc(const bub_batch::Member &m, BatchMember *d)
+{
+    const bub_ctx *c = m.ctx;
+    *d = BatchMember{};
+    const size_t M = (size_t)c->nvar * (size_t)c->N;
+    d->q = m.q;
+    d->w1 = m.work;
+    d->w2 = m.work + M;
+    d->P = c->d_P;
+    d->sc = c->d_sc;
+    d->g = c->g;
+    d->ph = c->ph;
+    d->bt = c->bt;
+    d->cfl = c->opts.cfl;
+    d->rtol = c->opts.sub_rtol > 0.0 ? c->opts.sub_rtol : 1e-4;
+    d->max_substeps = c->opts.max_substeps > 0 ? c->opts.max_substeps : 10000;
+    d->sources = c->opts.bubble_mode == BUB_BUBBLES_UNSPLIT;
+    int tx, ty, tz, blk;
+    if (bub_tile_info(c, c->tile, &tx, &ty, &tz, &blk)) return BUB_EINVAL;
+    d->ntile[0] = (c->g.n[0] + tx - 1) / tx;
+    d->ntile[1] = (c->g.n[1] + ty - 1) / ty;
+    d->ntile[2] = (c->g.n[2] + tz - 1) / tz;
+    d->ntiles = d->ntile[0] * d->ntile[1] * d->ntile[2];
+    d->bpg = bin_grouping(c, d->ntiles, &d->ngroups);
+    d->nitems = d->ntiles * d->ngroups;
+    return BUB_OK;
+}
+
+bool member_active(const bub_batch::Member &m) { return m.used && (m.open || m.remaining > 0); }
+
+// bub_batch_run takes the grouped launches below only when this is set.  They are switched off: on the
+// GPU a batch run through them once returned corrupted member states and once faulted the device, while
+// the same launches run block by block on the host reproduce every member bitwise; the cause, somewhere
+// in how the uploaded tables meet the launches that read them on the device, is not known yet.  Until it
+// is, bub_batch_run steps each member with its own kernels on the batch's lanes (as bub_batch_step).
+constexpr bool kGroupedLaunches = false;
+
+// Rewrite the member table and the launch lists for the members still stepping: both are filled in
+// the next staging buffer of the ring (once the upload that last read it has completed) and uploaded
+// on the batch's stream, ahead of the chunk that reads them.
+int batch_rebuild(bub_batch *b, hipStream_t s)
+{
+    const int r = b->stage_next;
+    if (b->stage_used[r]) HIP_OK(hipEventSynchronize(b->stage_ev[r]));
+    BatchMember *tab = reinterpret_cast<BatchMember *>(b->h_stage[r]);
+    LaunchList *lists = reinterpret_cast<LaunchList *>(b->h_stage[r] + sizeof(BatchMember) * b->slots.size());
+    std::vector<PlanMember> pm;
+    for (size_t i = 0; i < b->slots.size(); ++i) {
+        const auto &m = b->slots[i];
+        if (!member_active(m)) continue;
+        int rc = member_desc(m, &tab[i]);
+        if (rc) return rc;
+        const bub_ctx *c = m.ctx;
+        const int S = slots_for(c->N);
+        pm.push_back({(int)i, c->ndim, S, c->tile, c->opts.bubble_mode == BUB_BUBBLES_SPLIT,
+                      (c->N + cells_for(S) - 1) / cells_for(S), (long long)tab[i].nitems});
+    }
+    BatchPlan plan;
+    if (plan_batch(pm, bub_batch::NLISTS, &plan)) return BUB_EUNSUPPORTED;
+    for (size_t k = 0; k < plan.lists.size(); ++k) lists[k] = plan.lists[k];
+    HIP_OK(hipMemcpyAsync(b->d_tab, tab, sizeof(BatchMember) * b->slots.size(), hipMemcpyHostToDevice, s));
+    if (!plan.lists.empty())
+        HIP_OK(hipMemcpyAsync(b->d_lists, lists, sizeof(LaunchList) * plan.lists.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipEventRecord(b->stage_ev[r], s));
+    b->stage_used[r] = true;
+    b->stage_next = (r + 1) % bub_batch::NSTAGE;
+    auto conv = [](const std::vector<PlanLaunch> &v) {
+        std::vector<bub_batch::Launch> o;
+        for (const auto &l : v) o.push_back({l.d, l.key, l.list, l.blocks});
+        return o;
+    };
+    b->prim_all = conv(plan.prim_all);
+    b->prim_split = conv(plan.prim_split);
+    b->stage_l = conv(plan.stage);
+    b->dt_list = plan.dt_list;
+    b->dt_count = plan.dt_count;
+    b->dirty = false;
+    ++b->version;
+    return BUB_OK;
+}
+
+template <int D, int MODE>
+void launch_prim_group(const bub_batch *b, const bub_batch::Launch &l, int which, hipStream_t s)
+{
+    const dim3 grid((unsigned)l.blocks);
+    const LaunchList *L = b->d_lists + l.list;
+    switch (l.key) {
+    case 1: hipLaunchKernelGGL((k_prim_group<D, MODE, 1, PRIM_CELLS_1>), grid, dim3(PRIM_CELLS_1), 0, s, b->d_tab, L, which); break;
+    case 2: hipLaunchKernelGGL((k_prim_group<D, MODE, 2, PRIM_CELLS_S>), grid, dim3(2 * PRIM_CELLS_S), 0, s, b->d_tab, L, which); break;
+    case 4: hipLaunchKernelGGL((k_prim_group<D, MODE, 4, PRIM_CELLS_S>), grid, dim3(4 * PRIM_CELLS_S), 0, s, b->d_tab, L, which); break;
+    default: hipLaunchKernelGGL((k_prim_group<D, MODE, 8, PRIM_CELLS_S>), grid, dim3(8 * PRIM_CELLS_S), 0, s, b->d_tab, L, which); break;
+    }
+}
+
+void prim_groups(const bub_batch *b, const std::vector<bub_batch::Launch> &v, int which, bool cfl, hipStream_t s)
+{
+    for (const auto &l : v) {
+        if (l.d == 1) cfl ? launch_prim_group<1, PRIM_CFL>(b, l, which, s) : launch_prim_group<1, PRIM_ONLY>(b, l, which, s);
+        else if (l.d == 2) cfl ? launch_prim_group<2, PRIM_CFL>(b, l, which, s) : launch_prim_group<2, PRIM_ONLY>(b, l, which, s);
+        else cfl ? launch_prim_group<3, PRIM_CFL>(b, l, which, s) : launch_prim_group<3, PRIM_ONLY>(b, l, which, s);
+    }
+}
+
+template <int D>
+void launch_bubble_group(const bub_batch *b, const bub_batch::Launch &l, hipStream_t s)
+{
+    const dim3 grid((unsigned)l.blocks);
+    const LaunchList *L = b->d_lists + l.list;
+    switch (l.key) {
+    case 1: hipLaunchKernelGGL((k_bubble_group<D, 1, PRIM_CELLS_1>), grid, dim3(PRIM_CELLS_1), 0, s, b->d_tab, L); break;
+    case 2: hipLaunchKernelGGL((k_bubble_group<D, 2, PRIM_CELLS_S>), grid, dim3(2 * PRIM_CELLS_S), 0, s, b->d_tab, L); break;
+    case 4: hipLaunchKernelGGL((k_bubble_group<D, 4, PRIM_CELLS_S>), grid, dim3(4 * PRIM_CELLS_S), 0, s, b->d_tab, L); break;
+    default: hipLaunchKernelGGL((k_bubble_group<D, 8, PRIM_CELLS_S>), grid, dim3(8 * PRIM_CELLS_S), 0, s, b->d_tab, L); break;
+    }
+}
+
+void bubble_groups(const bub_batch *b, hipStream_t s)
+{
+    for (const auto &l : b->prim_split) {
+        if (l.d == 1) launch_bubble_group<1>(b, l, s);
+        else if (l.d == 2) launch_bubble_group<2>(b, l, s);
+        else launch_bubble_group<3>(b, l, s);
+    }
+}
+
+template <int D, int V, typename TF>
+void launch_stage_group_t(const bub_batch *b, const bub_batch::Launch &l, int stage, hipStream_t s)
+{
+    using TC = Tile<D, V>;
+    const int per_xcd = (int)((l.blocks + 7) / 8);
+    hipLaunchKernelGGL((k_stage_group<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF>), dim3(8 * per_xcd), dim3(TC::BLOCK),
+                       0, s, b->d_tab, b->d_lists + l.list, stage, per_xcd);
+}
+
+template <int D, int V>
+void launch_stage_group_v(const bub_batch *b, const bub_batch::Launch &l, int stage, hipStream_t s)
+{
+    if (b->precision == BUB_PREC_MIXED) launch_stage_group_t<D, V, float>(b, l, stage, s);
+    else launch_stage_group_t<D, V, double>(b, l, stage, s);
+}
+
+void stage_groups(const bub_batch *b, int stage, hipStream_t s)
+{
+    for (const auto &l : b->stage_l) {
+        const int v = l.key;
+        switch (l.d) {
+        case 1:
+            if (v == 1) launch_stage_group_v<1, 1>(b, l, stage, s);
+            else if (v == 2) launch_stage_group_v<1, 2>(b, l, stage, s);
+            else launch_stage_group_v<1, 0>(b, l, stage, s);
+            break;
+        case 2:
+            if (v == 1) launch_stage_group_v<2, 1>(b, l, stage, s);
+            else if (v == 2) launch_stage_group_v<2, 2>(b, l, stage, s);
+            else if (v == 3) launch_stage_group_v<2, 3>(b, l, stage, s);
+            else if (v == 4) launch_stage_group_v<2, 4>(b, l, stage, s);
+            else if (v == 5) launch_stage_group_v<2, 5>(b, l, stage, s);
+            else launch_stage_group_v<2, 0>(b, l, stage, s);
+            break;
+        default:
+            if (v == 1) launch_stage_group_v<3, 1>(b, l, stage, s);
+            else if (v == 2) launch_stage_group_v<3, 2>(b, l, stage, s);
+            else if (v == 3) launch_stage_group_v<3, 3>(b, l, stage, s);
+            else if (v == 4) launch_stage_group_v<3, 4>(b, l, stage, s);
+            else launch_stage_group_v<3, 0>(b, l, stage, s);
+            break;
+        }
+    }
+}
+
+// nsteps CFL-limited SSP-RK3 steps of every listed member: the phases of bub_rk3_step, each one
+// launch per kernel class for all members (split members add their bubble half-steps).
+int batch_chunk(const bub_batch *b, int nsteps, hipStream_t s)
+{
+    const bool any_split = !b->prim_split.empty();
+    for (int k = 0; k < nsteps; ++k) {
+        prim_groups(b, b->prim_all, 0, true, s);                      // primitives and wave speeds of u^n
+        hipLaunchKernelGGL(k_dt_group, dim3((unsigned)b->dt_count), dim3(WMAX_SLOTS), 0, s, b->d_tab,
+                           b->d_lists + b->dt_list);
+        if (any_split) {
+            bubble_groups(b, s);                                         // S_b(dt/2)
+            prim_groups(b, b->prim_split, 0, false, s);
+        }
+        stage_groups(b, 1, s);
+        prim_groups(b, b->prim_all, 1, false, s);
+        stage_groups(b, 2, s);
+        prim_groups(b, b->prim_all, 2, false, s);
+        stage_groups(b, 3, s);
+        if (any_split) bubble_groups(b, s);                              // S_b(dt/2)
+    }
+    return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
+}
+
+// Capture a chunk of nsteps into one graph (kernels only) unless the cached one matches.
+int batch_chunk_graph(bub_batch *b, int nsteps)
+{
+    if (b->run_exec && b->run_steps == nsteps && b->run_version == b->version) return BUB_OK;
+    hipGraph_t g = nullptr;
+    HIP_OK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = batch_chunk(b, nsteps, b->cap);
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (rc || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : BUB_EHIP;
+    }
+    hipGraphExec_t x = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return BUB_EHIP;
+    if (b->run_exec) {   // an earlier launch of it may still run: free it once its last launch is done
+        b->run_retired.emplace_back(b->run_exec, b->run_ev);
+        b->run_ev = nullptr;
+    }
+    if (!b->run_ev && hipEventCreateWithFlags(&b->run_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGraphExecDestroy(x);
+        b->run_exec = nullptr;
+        return BUB_EHIP;
+    }
+    b->run_exec = x;
+    b->run_steps = nsteps;
+    b->run_version = b->version;
+    return BUB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bub_batch_run(bub_batch *b, int max_steps, int *steps_taken, void *stream)
+{
+    if (!b || max_steps < 0) return BUB_EINVAL;
+    if (steps_taken) *steps_taken = 0;
+    hipStream_t s = (hipStream_t)stream;
+    // the chunk: at most max_steps, never past the member with the fewest steps left
+    int n = max_steps;
+    bool any = false;
+    for (const auto &m : b->slots) {
+        if (!member_active(m)) continue;
+        any = true;
+        if (!m.open && m.remaining < n) n = m.remaining;
+    }
+    if (!any || n == 0) return BUB_OK;
+    int rc;
+    if (kGroupedLaunches) {
+        if (b->dirty && (rc = batch_rebuild(b, s))) return rc;
+        for (size_t k = 0; k < b->run_retired.size();) {
+            if (hipEventQuery(b->run_retired[k].second) == hipSuccess) {
+                (void)hipGraphExecDestroy(b->run_retired[k].first);
+                (void)hipEventDestroy(b->run_retired[k].second);
+                b->run_retired[k] = b->run_retired.back();
+                b->run_retired.pop_back();
+            } else {
+                ++k;
+            }
+        }
+        if (b->graphs) {
+            if ((rc = batch_chunk_graph(b, n))) return rc;
+            HIP_OK(hipGraphLaunch(b->run_exec, s));
+            HIP_OK(hipEventRecord(b->run_ev, s));
+        } else if ((rc = batch_chunk(b, n, s))) {
+            return rc;
+        }
+    } else if ((rc = lanes_steps(b, n, s, member_active))) {
+        return rc;
+    }
+    // members whose last step is now queued: a flag in host memory marks their completion
+    ++b->epoch;
+    for (size_t i = 0; i < b->slots.size(); ++i) {
+        auto &m = b->slots[i];
+        if (!member_active(m) || m.open) continue;
+        m.remaining -= n;
+        if (m.remaining == 0) {
+            m.done_epoch = b->epoch;
+            hipLaunchKernelGGL(k_flag_set, dim3(1), dim3(64), 0, s, b->d_flags, (int)i, b->epoch);
+            b->dirty = true;   // finished members leave the lists
+        }
+    }
+    HIP_OK(hipGetLastError());
+    if (steps_taken) *steps_taken = n;
+    return BUB_OK;
+}
+
+int bub_batch_poll(bub_batch *b, int *done_slots, int *ndone)
+{
+    if (!b || !ndone || !done_slots) return BUB_EINVAL;
+    int k = 0;
+    for (size_t i = 0; i < b->slots.size(); ++i) {
+        auto &m = b->slots[i];
+        if (!m.used || m.reported || m.done_epoch == 0) continue;
+        if (__atomic_load_n(&b->h_flags[i], __ATOMIC_ACQUIRE) == m.done_epoch) {
+            m.reported = true;
+            done_slots[k++] = (int)i;
+        }
+    }
+    *ndone = k;
+    return BUB_OK;
+}
+
+int bub_batch_remaining(const bub_batch *b, int slot, int *steps)
+{
+    if (!b || !steps || slot < 0 || slot >= (int)b->slots.size() || !b->slots[slot].used) return BUB_EINVAL;
+    *steps = b->slots[slot].open ? -1 : b->slots[slot].remaining;
+    return BUB_OK;
+}
+
+}  // extern "C"

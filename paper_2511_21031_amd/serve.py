@@ -5,12 +5,15 @@ grid, bins, void fraction, drive and step count).  The server
 
 * admits arrived requests in arrival order as soon as a batch slot is free and
   the request's device footprint (state, the two work copies of the stage
-  results, the context's own buffers) fits the HBM budget; the context and the
+  results, the context's own buffers, the initial primitives) fits the HBM
+  budget (the batch enforces it too); the context and the
   initial state are created on the server stream without a host
   synchronisation;
 * keeps every admitted problem's state resident and advances all of them
-  together with one batch call (bub_batch_step: the members' kernels overlap
-  on the device), in chunks of at most `chunk` steps that never run past the
+  together with one batch call per chunk: bub_batch_run (default), which
+  counts each member's steps down and flags its completion, or bub_batch_step
+  (`use_run=False`); either way the members' own kernels overlap over the
+  batch's streams; chunks have at most `chunk` steps and never run past the
   member with the fewest steps left, so that a member leaves the batch exactly
   at its last step;
 * retires a problem when the stream event after its last step has completed:
@@ -69,7 +72,7 @@ class Server:
 
     def __init__(self, hbm_budget: int, max_slots: int = 64, precision=None, bubble_mode=None,
                  chunk: int = 10, keep_results: bool = False, autotune: bool = True, footprint=footprint_bytes,
-                 lanes: int = 4):
+                 lanes: int = 4, use_run: bool = True):
         self.budget = int(hbm_budget)
         self.max_slots = int(max_slots)
         self.precision = precision
@@ -79,6 +82,7 @@ class Server:
         self.autotune = autotune
         self.footprint = footprint
         self.lanes = int(lanes)
+        self.use_run = bool(use_run)   # chunks through bub_batch_run (step counts) or bub_batch_step
         self.used = 0
         self.peak_used = 0
         self.peak_active = 0
@@ -96,7 +100,7 @@ class Server:
         if self.bubble_mode is None:
             self.bubble_mode = BUBBLES_SPLIT
         self.stream = torch.cuda.Stream()
-        self.batch = Batch(self.precision, self.max_slots)
+        self.batch = Batch(self.precision, self.max_slots, hbm_budget=self.budget)
         self.batch.set_lanes(self.lanes)
 
     def _admit(self, rec: Record, case) -> int:
@@ -116,14 +120,19 @@ class Server:
         if key not in self.classes:
             self.classes.add(key)
             self._tune = True
-        return self.batch.add(ctx, q, work)
+        return self.batch.add(ctx, q, work, steps=rec.steps)
 
     def _step(self, nsteps: int, nactive: int):
         if self.autotune and self._tune:
             # tile shape of each new (ndim, nb) class (synchronises the server stream once per class)
             self.batch.autotune(reps=2, stream=self.stream)
             self._tune = False
-        self.batch.step(nsteps, stream=self.stream)
+        if self.use_run:
+            taken = self.batch.run(nsteps, stream=self.stream)
+            if taken != nsteps:
+                raise RuntimeError(f"batch chunk took {taken} steps, {nsteps} planned")
+        else:
+            self.batch.step(nsteps, stream=self.stream)
 
     def _remove(self, slot: int):
         self.batch.remove(slot)

@@ -1,10 +1,11 @@
 """Batches of resident problems and the continuous-batching server on the GPU.
 
-A batch member runs exactly the kernels of bub_rk3_step on its own buffers
-(only the stream it is queued on and the tile shape the class autotuner picks
-may differ, and results do not depend on either), so its state after k batched
-steps must be bitwise the state after k bub_rk3_step calls on its own context,
-whatever the other members are and whenever the member joined.  The server's
+A batch member runs the arithmetic of bub_rk3_step on its own buffers (its own
+kernels on one of the batch's lanes; only the stream, the block order and the
+tile shape the class autotuner picks may differ, and results depend on none of
+them), so its state after k batched steps must be bitwise the state after k
+bub_rk3_step calls on its own context, whatever the other members are and
+whenever the member joined.  The server's
 results must likewise be bitwise the results of each request solved alone, and
 stay within the split-mode bound of the FP64 oracle run on its own.
 """
@@ -70,38 +71,97 @@ def _join(torch, bub, batch, case, split, prec):
     return batch.add(ctx, q, work), (ctx, q, work)
 
 
-PERSISTENT_SKIP = ("written for the first batch design, a persistent stage kernel pulling (member, tile) items "
-                   "from a device table; its first device run ended in a memory fault whose cause was not found "
-                   "(a host-side emulation of the same sequence under AddressSanitizer is clean), so that kernel "
-                   "was removed; the stream batch below replaces it")
+GROUPED_OFF = ("the grouped launches of bub_batch_run are switched off in the library: on the GPU they once "
+               "returned corrupted member states and once faulted the device; run block by block on the host "
+               "they reproduce every member bitwise, and the device-side cause is not found yet")
 
 
-@pytest.mark.skip(reason=PERSISTENT_SKIP)
+@pytest.mark.skip(reason=GROUPED_OFF)
+@pytest.mark.parametrize("graphs", [True, False])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_batch_members_bitwise_equal_alone(torch, bub, prec):
+def test_grouped_batch_members_bitwise_equal_alone(torch, bub, prec, graphs):
+    """bub_batch_run in its grouped form: one launch per phase and kernel class for every member (one
+    graph launch per chunk)."""
+    _run_members_join_leave(torch, bub, prec, graphs)
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_run_members_bitwise_equal_alone(torch, bub, prec, graphs):
+    """bub_batch_run: members with their own step counts join and leave; each ends bitwise equal to its
+    problem stepped alone, and bub_batch_poll reports every member once, after its last step has
+    completed."""
+    _run_members_join_leave(torch, bub, prec, graphs)
+
+
+def _run_members_join_leave(torch, bub, prec, graphs):
     P = bub.PREC_FP64 if prec == "fp64" else bub.PREC_MIXED
     mem = _members()
+    want = {"c1": 5, "2d_periodic": 3, "3d_reflective": 6, "3d_collapse_split": 4, "request_split": 2}
     batch = bub.Batch(P, max_cases=8)
-    slots, held, steps = {}, {}, {}
+    batch.set_graphs(graphs)
+    slots, held = {}, {}
     for name, case, split in mem[:4]:
-        slots[name], held[name] = _join(torch, bub, batch, case, split, P)
-        steps[name] = 0
-    batch.step(3)
-    for name in slots:
-        steps[name] += 3
-    batch.remove(slots.pop("2d_periodic"))
-    name, case, split = mem[4]
-    slots[name], held[name] = _join(torch, bub, batch, case, split, P)
-    steps[name] = 0
-    batch.step(2)
-    for name in slots:
-        steps[name] += 2
+        ctx, q, work = _fresh(torch, bub, case, split, P)
+        slots[name] = batch.add(ctx, q, work, steps=want[name])
+        held[name] = (ctx, q, work)
+    assert batch.run(10) == 3                       # never past the member with the fewest steps left
     torch.cuda.synchronize()
+    assert batch.poll() == [slots["2d_periodic"]]
+    assert batch.poll() == []
+    batch.remove(slots["2d_periodic"])
+    name, case, split = mem[4]
+    ctx, q, work = _fresh(torch, bub, case, split, P)
+    slots[name] = batch.add(ctx, q, work, steps=want[name])
+    held[name] = (ctx, q, work)
+    reported, chunks = [], []
+    while True:
+        n = batch.run(10)
+        if n == 0:
+            break
+        chunks.append(n)
+        reported += batch.poll()
+    assert chunks == [1, 1, 1] and sum(chunks) + 3 == want["3d_reflective"]
+    torch.cuda.synchronize()
+    reported += batch.poll()
+    assert sorted(reported) == sorted(slots[k] for k in want if k != "2d_periodic")
+    assert all(batch.remaining(slots[k]) == 0 for k in want if k != "2d_periodic")
+    diffs = {}
     for name, case, split in mem:
         ctx, q, _ = held[name]
         assert ctx.last_error()[0] == 0, name
-        ref = _alone(torch, bub, case, split, P, steps[name])
-        assert torch.equal(q, ref), (name, (q - ref).abs().max().item())
+        ref = _alone(torch, bub, case, split, P, want[name])
+        diffs[name] = [] if torch.equal(q, ref) else (q - ref).abs().amax(dim=1).tolist()
+    print("members differing from their problem alone (max |diff| per row):",
+          {k: v for k, v in diffs.items() if v})
+    assert not any(diffs.values())
+    batch.close()
+
+
+def test_batch_run_open_members_and_budget(torch, bub):
+    """Open-ended members (steps = 0) take every chunk and are never reported; the byte budget refuses a
+    member that does not fit and takes one again after a removal."""
+    P = bub.PREC_FP64
+    mem = _members()
+    a = _fresh(torch, bub, mem[0][1], False, P)
+    b = _fresh(torch, bub, mem[1][1], False, P)
+    need_a = 3 * a[0].state_bytes + bub.ctx_buffer_bytes(a[0].ndim, a[0].n, a[0].nb)
+    need_b = 3 * b[0].state_bytes + bub.ctx_buffer_bytes(b[0].ndim, b[0].n, b[0].nb)
+    batch = bub.Batch(P, max_cases=4, hbm_budget=need_a + need_b - 1)
+    sa = batch.add(*a)
+    with pytest.raises(bub.BubblyError) as e:
+        batch.add(*b)
+    assert e.value.code == -2
+    assert batch.run(4) == 4 and batch.run(3) == 3
+    torch.cuda.synchronize()
+    assert batch.poll() == [] and batch.remaining(sa) == -1
+    assert torch.equal(a[1], _alone(torch, bub, mem[0][1], False, P, 7))
+    batch.remove(sa)
+    sb = batch.add(*b, steps=2)
+    assert batch.run(4) == 2
+    torch.cuda.synchronize()
+    assert batch.poll() == [sb]
+    assert torch.equal(b[1], _alone(torch, bub, mem[1][1], False, P, 2))
     batch.close()
 
 
@@ -205,14 +265,15 @@ def _moment_errors(orc, pb, got, ref):
     return {"p": rel_err(mg[6], mr[6]), "alpha": rel_err(mg[1], mr[1])}
 
 
-def test_server_results_equal_alone_and_match_oracle(torch, bub, orc):
+@pytest.mark.parametrize("use_run", [True, False])
+def test_server_results_equal_alone_and_match_oracle(torch, bub, orc, use_run):
     from paper_2511_21031_amd.serve import Server, footprint_bytes
     reqs = W.c5_stream(count=24, seed=7, scale=0.05)
     cases = {r.rid: W.request_case(r) for r in reqs}
     fps = [footprint_bytes(c) for c in cases.values()]
     budget = 3 * max(fps)
     srv = Server(budget, max_slots=6, precision=bub.PREC_MIXED, bubble_mode=bub.BUBBLES_SPLIT, chunk=4,
-                 keep_results=True)
+                 keep_results=True, use_run=use_run)
     recs = srv.run(reqs, lambda r: cases[r.rid], time_scale=0.0)
     print(f"peak resident {srv.peak_active} problems, {srv.peak_used} of {budget} B; {len(srv.chunks)} step calls")
     assert srv.peak_used <= budget and srv.peak_active >= 2 and srv.used == 0
