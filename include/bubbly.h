@@ -59,8 +59,13 @@ enum { BUB_PREC_FP64 = 0, BUB_PREC_MIXED = 1 };
 enum { BUB_BUBBLES_UNSPLIT = 0, BUB_BUBBLES_SPLIT = 1 };
 
 /* Cartesian grid.  ndim in {1,2,3}; n[d] = 1 and dx[d] ignored for d >= ndim.
- * bc[d][0/1] = low/high boundary of direction d: periodic (both ends) or
- * reflective (mirror ghost cells, normal velocity negated; needs n[d] >= 3). */
+ * bc[d][0/1] = low/high boundary of direction d, both ends alike: 0 periodic,
+ * 1 reflective (mirror ghost cells, normal velocity negated; needs n[d] >= 3)
+ * or 2 non-reflective (Sec. 5.1, after Thompson: every ghost cell takes the
+ * boundary cell's state, so the Riemann problem at the boundary face has no
+ * jump and no wave enters through it; an outgoing plane wave at normal
+ * incidence leaves with a reflection of order 1e-5 of its amplitude at 12
+ * cells per pulse width).  The Lagrangian calls take 0 and 1 only. */
 typedef struct { int ndim; int n[3]; double dx[3]; int bc[3][2]; } bub_grid;
 
 /* Stiffened-gas liquid, eq. eos_liquid: p_l = (gamma-1) rho_l e_l - gamma pi_inf.
@@ -151,6 +156,35 @@ int bub_rhs_stage(bub_ctx *ctx, const double *q, double *rhs, void *stream);
  * double, may be NULL) receives the step used.  In split mode the step is
  * S_b(dt/2) S_f(dt) S_b(dt/2) (Strang splitting, Sec. 3). */
 int bub_rk3_step(bub_ctx *ctx, double *q, double *work, double dt, double *dt_dev, void *stream);
+
+/* One-way planar acoustic source (Sec. 2: forcing of the mass, momentum and
+ * energy equations on a source plane; the Sec. 5.1 set-ups are driven this
+ * way).  The plane is normal to axis `dir` (< ndim) at coordinate x (cell i has
+ * its centre at (i + 1/2) dx[dir]); sign = +1 emits toward +dir, -1 toward
+ * -dir.  The emitted pressure wave is amp sin(2 pi freq (t - t0)) for t0 <= t <=
+ * t0 + ncycles/freq (ncycles = 0: from t0 on), delayed by the travel time from
+ * the plane, with nothing emitted upstream.  Forcing, about the reference
+ * liquid state (c0 = sqrt(gamma (p0 + pi_inf) / rho0)): S_p = c0 A(t) g(s),
+ * S_rho = S_p / c0^2, S_m = sign S_p / c0 along dir, S_E = (1 - alpha) S_p /
+ * (gamma - 1) + u.S_m - |u|^2 S_rho / 2, with g the normal pdf of standard
+ * deviation `width` (cut at 6 widths) of the distance s from the plane, and A
+ * the sine with its amplitude raised by exp((2 pi freq width / c0)^2 / 2),
+ * the factor the Gaussian's smoothing takes off it.  RK stages evaluate the
+ * source at the time of their input state (t, t + dt, t + dt/2). */
+typedef struct { int dir; int sign; double x, width, amp, freq, t0, ncycles; } bub_source;
+
+/* Set (src non-NULL) or clear (NULL) the context's source.  BUB_EINVAL if dir >=
+ * ndim, sign is not +-1, width <= 0, freq <= 0, ncycles < 0 or amp is not
+ * finite.  The source is added by a pass after each stage kernel (so the
+ * stages take a separate primitive pass while one is set). */
+int bub_set_source(bub_ctx *ctx, const bub_source *src);
+
+/* The context's clock: the time of the state.  Every RK step advances it by
+ * its dt on the device; bub_set_time sets it (ordered on `stream`), and
+ * bub_get_time reads it (waits for the device).  A new context starts at 0.
+ * bub_rhs_stage evaluates the source at the clock's time. */
+int bub_set_time(bub_ctx *ctx, double t, void *stream);
+int bub_get_time(bub_ctx *ctx, double *t);
 
 /* nsteps calls of bub_rk3_step in one (same arguments; dt_dev receives the last
  * step's dt).  Results are bitwise those of nsteps separate calls.  In unsplit
@@ -274,9 +308,8 @@ int bub_batch_destroy(bub_batch *batch);
  * stepped by every run and never reported done); *slot receives its handle.
  * BUB_ENOMEM if its bytes (3 state copies + bub_ctx_buffer_bytes) exceed what
  * the budget has left; BUB_EINVAL if the batch is full, steps < 0, the precision
- * differs, the context is already a member, or q and work overlap;
- * BUB_EUNSUPPORTED for a viscous context (opts.viscous = 1).  A member whose
- * (ndim, nb) class was autotuned gets that class's stage tile shape. */
+ * differs, the context is already a member, or q and work overlap.  A member
+ * whose (ndim, nb) class was autotuned gets that class's stage tile shape. */
 int bub_batch_add(bub_batch *batch, bub_ctx *ctx, double *q, double *work, int steps, int *slot);
 /* Remove a member (its bytes return to the budget).  Its buffers must stay
  * valid until the work already enqueued for it has finished. */

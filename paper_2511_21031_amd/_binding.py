@@ -45,6 +45,12 @@ class _Opts(ctypes.Structure):
                 ("sub_rtol", ctypes.c_double), ("max_substeps", ctypes.c_int), ("viscous", ctypes.c_int)]
 
 
+class _Source(ctypes.Structure):
+    _fields_ = [("dir", ctypes.c_int), ("sign", ctypes.c_int), ("x", ctypes.c_double), ("width", ctypes.c_double),
+                ("amp", ctypes.c_double), ("freq", ctypes.c_double), ("t0", ctypes.c_double),
+                ("ncycles", ctypes.c_double)]
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -65,6 +71,9 @@ _SIGS = {
     "bub_init_state": [_vp, _vp, _vp, _vp],
     "bub_rhs_stage": [_vp, _vp, _vp, _vp],
     "bub_rk3_step": [_vp, _vp, _vp, ctypes.c_double, _vp, _vp],
+    "bub_set_source": [_vp, ctypes.POINTER(_Source)],
+    "bub_set_time": [_vp, ctypes.c_double, _vp],
+    "bub_get_time": [_vp, ctypes.POINTER(ctypes.c_double)],
     "bub_rk3_steps": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double, _vp, _vp],
     "bub_moments": [_vp, _vp, _vp, _vp],
     "bub_last_error": [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_int),
@@ -149,7 +158,7 @@ class Context:
 
     def __init__(self, ndim, n, dx, bc, nb, r0_median=10e-6, sigma_ln=0.3, liquid=None, gas=None, cfl=0.3,
                  precision=PREC_FP64, bubble_mode=BUBBLES_UNSPLIT, sub_rtol=1e-4, max_substeps=10000,
-                 torch_buffer=False, stream=None, viscous=0):
+                 torch_buffer=False, stream=None, viscous=0, source=None):
         """torch_buffer=True: the context's device memory is a torch tensor and it is initialised on
         `stream` (bub_ctx_create_on): no allocation call and no host synchronisation."""
         L = lib()
@@ -192,6 +201,8 @@ class Context:
                             ctypes.byref(wb)), "bub_layout")
         self.nvar, self.nprim, self.ncells = nv.value, npr.value, nc.value
         self.state_bytes, self.work_bytes = sb.value, wb.value
+        if source is not None:
+            self.set_source(source)
 
     # -- lifetime -------------------------------------------------------------
     def close(self):
@@ -237,6 +248,24 @@ class Context:
         rhs = torch.empty_like(q) if rhs is None else rhs
         _check(lib().bub_rhs_stage(self._h, _ptr(q), _ptr(rhs), _stream(stream)), "bub_rhs_stage")
         return rhs
+
+    def set_source(self, src: dict | None):
+        """One-way planar acoustic source: dict(dir, sign, x, width, amp, freq, t0=0, ncyc=0), or None."""
+        if src is None:
+            _check(lib().bub_set_source(self._h, None), "bub_set_source")
+            return
+        so = _Source(int(src["dir"]), int(src["sign"]), float(src["x"]), float(src["width"]), float(src["amp"]),
+                     float(src["freq"]), float(src.get("t0", 0.0)), float(src.get("ncyc", 0.0)))
+        _check(lib().bub_set_source(self._h, ctypes.byref(so)), "bub_set_source")
+
+    def set_time(self, t: float, stream=None):
+        _check(lib().bub_set_time(self._h, float(t), _stream(stream)), "bub_set_time")
+
+    def time(self) -> float:
+        """The context's clock (waits for the device)."""
+        v = ctypes.c_double()
+        _check(lib().bub_get_time(self._h, ctypes.byref(v)), "bub_get_time")
+        return v.value
 
     def rk3_step(self, q: torch.Tensor, work: torch.Tensor, dt: float = 0.0, dt_dev: torch.Tensor | None = None,
                  stream=None):

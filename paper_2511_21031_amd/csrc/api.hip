@@ -19,6 +19,7 @@
 #include "batch_kernels.hpp"
 #include "batch_plan.hpp"
 #include "viscous_kernel.hpp"
+#include "source_kernel.hpp"
 
 #include <vector>
 #include "ctx.hpp"
@@ -269,22 +270,74 @@ int stage_kernel(bub_ctx *c, const StageArgs &A, hipStream_t s)
     }
 }
 
-// An RK stage (or a right-hand side): the stage kernel, then, for a viscous problem, the viscous
-// pass that adds the stress of eq. stressTensor to the momentum and energy the kernel wrote.
-int stage(bub_ctx *c, const StageArgs &A, hipStream_t s)
+// The source pass: the launch description of the context's source (cells that can lie within 6
+// widths of the plane); false when no cell can.
+bool source_launch(const bub_ctx *c, Source *S)
+{
+    const bub_source &q = c->src;
+    const int d = q.dir;
+    const double dx = c->grid.dx[d];
+    const int n = c->g.n[d];
+    long long lo = (long long)std::floor((q.x - 6.0 * q.width) / dx - 0.5) - 1;
+    long long hi = (long long)std::ceil((q.x + 6.0 * q.width) / dx - 0.5) + 1;
+    if (lo < 0) lo = 0;
+    if (hi > n - 1) hi = n - 1;
+    if (hi < lo) return false;
+    const double c0 = std::sqrt(c->liq.gamma * (c->liq.p0 + c->liq.pi_inf) / c->liq.rho0);
+    const double k = 2.0 * M_PI * q.freq / c0;
+    *S = Source{};
+    S->dir = d;
+    S->sign = q.sign;
+    S->lo = (int)lo;
+    for (int e = 0; e < 3; ++e) S->m[e] = e == d ? (int)(hi - lo + 1) : c->g.n[e];
+    S->x = q.x;
+    S->width = q.width;
+    S->dx = dx;
+    S->norm = 1.0 / (std::sqrt(2.0 * M_PI) * q.width);
+    S->amp_eff = q.amp * std::exp(0.5 * (k * q.width) * (k * q.width));
+    S->omega = 2.0 * M_PI * q.freq;
+    S->t0 = q.t0;
+    S->dur = q.ncycles > 0.0 ? q.ncycles / q.freq : 0.0;
+    S->c0 = c0;
+    S->inv_c0 = 1.0 / c0;
+    S->inv_gm1 = 1.0 / (c->liq.gamma - 1.0);
+    return true;
+}
+
+// An RK stage (or a right-hand side): the stage kernel, then the passes that add what the stage kernels
+// carry no code for: the stress of eq. stressTensor (viscous problems) and the acoustic source.  tc: the
+// stage's time within the step (0, 1, 1/2 for stages 1, 2, 3; negative for a right-hand side).
+int stage(bub_ctx *c, const StageArgs &A, hipStream_t s, double tc)
 {
     int rc = stage_kernel(c, A, s);
-    if (rc || !c->opts.viscous || !(c->gas.mu > 0.0)) return rc;
-    long pr = prof_begin(c, BUB_K_OTHER, s);
-    const dim3 grid(blocks_for(c->N)), block(256);
-    const double *dtp = A.rhs_mode ? nullptr : A.dtp;
-    switch (c->ndim) {
-    case 1: hipLaunchKernelGGL((k_viscous<1>), grid, block, 0, s, A.P, A.qo, c->g, c->gas.mu, dtp, A.b); break;
-    case 2: hipLaunchKernelGGL((k_viscous<2>), grid, block, 0, s, A.P, A.qo, c->g, c->gas.mu, dtp, A.b); break;
-    default: hipLaunchKernelGGL((k_viscous<3>), grid, block, 0, s, A.P, A.qo, c->g, c->gas.mu, dtp, A.b); break;
+    if (rc) return rc;
+    if (c->opts.viscous && c->gas.mu > 0.0) {
+        long pr = prof_begin(c, BUB_K_OTHER, s);
+        const dim3 grid(blocks_for(c->N)), block(256);
+        const double *dtp = A.rhs_mode ? nullptr : A.dtp;
+        switch (c->ndim) {
+        case 1: hipLaunchKernelGGL((k_viscous<1>), grid, block, 0, s, A.P, A.qo, c->g, c->gas.mu, dtp, A.b); break;
+        case 2: hipLaunchKernelGGL((k_viscous<2>), grid, block, 0, s, A.P, A.qo, c->g, c->gas.mu, dtp, A.b); break;
+        default: hipLaunchKernelGGL((k_viscous<3>), grid, block, 0, s, A.P, A.qo, c->g, c->gas.mu, dtp, A.b); break;
+        }
+        prof_end(c, pr, s);
+        HIP_OK(hipGetLastError());
     }
-    prof_end(c, pr, s);
-    return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
+    Source S;
+    if (c->src_on && source_launch(c, &S)) {
+        long pr = prof_begin(c, BUB_K_OTHER, s);
+        const long long cells = (long long)S.m[0] * S.m[1] * S.m[2];
+        const dim3 grid((unsigned)std::min<long long>((cells + 255) / 256, 2048)), block(256);
+        const double t = A.rhs_mode ? -1.0 : tc;
+        switch (c->ndim) {
+        case 1: hipLaunchKernelGGL((k_source<1>), grid, block, 0, s, A.P, A.qo, c->g, S, c->d_sc, t, A.b); break;
+        case 2: hipLaunchKernelGGL((k_source<2>), grid, block, 0, s, A.P, A.qo, c->g, S, c->d_sc, t, A.b); break;
+        default: hipLaunchKernelGGL((k_source<3>), grid, block, 0, s, A.P, A.qo, c->g, S, c->d_sc, t, A.b); break;
+        }
+        prof_end(c, pr, s);
+        HIP_OK(hipGetLastError());
+    }
+    return BUB_OK;
 }
 
 // Tiles of the context's current stage shape.
@@ -300,8 +353,8 @@ long long stage_tiles(const bub_ctx *c)
 // one thread per cell (then both forms sum the bins in the same order, so results are bitwise equal).
 bool stage_fusable(const bub_ctx *c)
 {
-    // (a viscous pass after the stage changes the state the epilogue would describe)
-    if (!c->d_P2 || slots_for(c->N) != 1 || c->opts.viscous) return false;
+    // (a viscous or source pass after the stage changes the state the epilogue would describe)
+    if (!c->d_P2 || slots_for(c->N) != 1 || c->opts.viscous || c->src_on) return false;
     int groups = 0;
     bin_grouping(c, stage_tiles(c), &groups);
     return groups == 1;
@@ -344,6 +397,16 @@ __global__ void k_ctx_init(double *bins, BinTable t, int n, Scalars *sc)
         sc->err_code = 0;
         sc->err_bin = 0;
         sc->err_cell = 0;
+        sc->t = 0.0;
+        sc->t_next = 0.0;
+    }
+}
+
+__global__ void k_set_time(Scalars *sc, double t)
+{
+    if (threadIdx.x == 0) {
+        sc->t = t;
+        sc->t_next = t;
     }
 }
 
@@ -398,7 +461,7 @@ int ctx_fill(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, co
         if (d < grid->ndim) {
             if (!(grid->dx[d] > 0.0)) return BUB_EINVAL;
             int lo = grid->bc[d][0], hi = grid->bc[d][1];
-            if ((lo != 0 && lo != 1) || lo != hi) return BUB_EINVAL;
+            if (lo < 0 || lo > 2 || lo != hi) return BUB_EINVAL;
             if (lo == 1 && grid->n[d] < 3) return BUB_EINVAL;
         }
         N *= grid->n[d];
@@ -622,7 +685,7 @@ int rhs_stage_impl(bub_ctx *c, const double *q, double *rhs, hipStream_t s)
     A.b = 1.0;
     A.rhs_mode = 1;
     A.sources = c->opts.bubble_mode == BUB_BUBBLES_UNSPLIT;
-    return stage(c, A, s);
+    return stage(c, A, s, -1.0);
 }
 
 }  // namespace
@@ -675,20 +738,20 @@ int rk3_steps_impl(bub_ctx *c, double *q, double *work, int nsteps, double dt, d
         A.qk = q; A.qn = nullptr; A.qo = w1; A.a = 0.0; A.b = 1.0;
         A.P = Pa;
         A.Pout = fuse ? Pb : nullptr;
-        if ((rc = stage(c, A, s))) return rc;
+        if ((rc = stage(c, A, s, 0.0))) return rc;
         // stage 2: u2 = 3/4 u^n + 1/4 (u1 + dt L(u1))
         if (!fuse && (rc = prim(c, w1, Pa, PRIM_ONLY, s))) return rc;
         A.qk = w1; A.qn = q; A.qo = w2; A.a = 0.75; A.b = 0.25;
         A.P = fuse ? Pb : Pa;
         A.Pout = fuse ? Pa : nullptr;
-        if ((rc = stage(c, A, s))) return rc;
+        if ((rc = stage(c, A, s, 1.0))) return rc;
         // stage 3: u^{n+1} = 1/3 u^n + 2/3 (u2 + dt L(u2)), written over u^n (own-cell reads only)
         if (!fuse && (rc = prim(c, w2, Pa, PRIM_ONLY, s))) return rc;
         A.qk = w2; A.qn = q; A.qo = q; A.a = 1.0 / 3.0; A.b = 2.0 / 3.0;
         A.P = Pa;
         A.Pout = carry && more ? Pb : nullptr;
         A.cfl = carry && more && cfl;
-        if ((rc = stage(c, A, s))) return rc;
+        if ((rc = stage(c, A, s, 0.5))) return rc;
         if (split &&   // S_b(dt/2)
             (rc = bubble(c, q, &c->d_sc->dt, 0.5, 0.0,
                          c->nsub_diag ? c->nsub_diag + (size_t)c->nb * c->N : nullptr, s)))
@@ -739,7 +802,7 @@ int el_grid(const bub_ctx *c, ElGrid *g)
     for (int d = 0; d < 3; ++d) {
         g->n[d] = c->g.n[d];
         g->bc[d] = c->g.bc[d];
-        if (g->n[d] < 3) return BUB_EUNSUPPORTED;
+        if (g->n[d] < 3 || g->bc[d] > 1) return BUB_EUNSUPPORTED;   // periodic or reflective only
     }
     g->dx = c->grid.dx[0];
     g->inv_dx = 1.0 / g->dx;
@@ -955,6 +1018,40 @@ int bub_substep_counts(bub_ctx *c, int32_t *nsub)
     return BUB_OK;
 }
 
+int bub_set_source(bub_ctx *c, const bub_source *src)
+{
+    if (!c) return BUB_EINVAL;
+    if (!src) {
+        c->src_on = false;
+        return BUB_OK;
+    }
+    if (src->dir < 0 || src->dir >= c->ndim || (src->sign != 1 && src->sign != -1)) return BUB_EINVAL;
+    if (!(src->width > 0.0) || !(src->freq > 0.0) || !(src->ncycles >= 0.0) || !std::isfinite(src->amp) ||
+        !std::isfinite(src->x) || !std::isfinite(src->t0) || src->width == INFINITY || src->freq == INFINITY)
+        return BUB_EINVAL;
+    c->src = *src;
+    c->src_on = true;
+    return BUB_OK;
+}
+
+int bub_set_time(bub_ctx *c, double t, void *stream)
+{
+    if (!c || !std::isfinite(t)) return BUB_EINVAL;
+    hipLaunchKernelGGL(k_set_time, dim3(1), dim3(64), 0, (hipStream_t)stream, c->d_sc, t);
+    HIP_OK(hipGetLastError());
+    return BUB_OK;
+}
+
+int bub_get_time(bub_ctx *c, double *t)
+{
+    if (!c || !t) return BUB_EINVAL;
+    HIP_OK(hipDeviceSynchronize());
+    Scalars h{};
+    HIP_OK(hipMemcpy(&h, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost));
+    *t = h.t_next;
+    return BUB_OK;
+}
+
 int bub_bin_groups(bub_ctx *c, int groups)
 {
     if (!c || groups < 0) return BUB_EINVAL;
@@ -1027,10 +1124,10 @@ int bub_autotune(bub_ctx *c, const double *q, double *scratch, int reps, double 
     int best_v = keep;
     for (int v = 0; v < TILE_COUNT[c->ndim] && rc == BUB_OK; ++v) {
         c->tile = v;
-        rc = stage(c, A, s);  // warm-up (code load)
+        rc = stage_kernel(c, A, s);  // warm-up (code load)
         if (rc) break;
         if (hipEventRecord(e0, s) != hipSuccess) { rc = BUB_EHIP; break; }
-        for (int r = 0; r < reps && rc == BUB_OK; ++r) rc = stage(c, A, s);
+        for (int r = 0; r < reps && rc == BUB_OK; ++r) rc = stage_kernel(c, A, s);
         if (rc) break;
         float ms = 0.0f;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -1140,6 +1237,14 @@ struct bub_batch {
 };
 
 namespace {
+
+// bub_batch_run takes the grouped launches (further below) only when this is set.  They are switched
+// off: on the GPU a batch run through them once returned corrupted member states and once faulted the
+// device, while the same launches run block by block on the host reproduce every member bitwise; the
+// cause, somewhere in how the uploaded tables meet the launches that read them on the device, is not
+// known yet.  Until it is, bub_batch_run steps each member with its own kernels on the batch's lanes
+// (as bub_batch_step).
+constexpr bool kGroupedLaunches = false;
 
 // Whether p lies in device memory of the current HIP runtime (host memory, pinned or not, does not).
 bool is_device_memory(const void *p)
@@ -1276,7 +1381,8 @@ int bub_batch_add(bub_batch *b, bub_ctx *c, double *q, double *work, int steps, 
 {
     if (!b || !c || !q || !work || !slot || steps < 0) return BUB_EINVAL;
     if (c->opts.precision != b->precision) return BUB_EINVAL;
-    if (c->opts.viscous) return BUB_EUNSUPPORTED;   // the grouped launches carry no viscous pass
+    if (kGroupedLaunches && (c->opts.viscous || c->src_on))
+        return BUB_EUNSUPPORTED;   // the grouped launches carry no viscous or source pass
     const size_t M = (size_t)c->nvar * (size_t)c->N;
     if ((q >= work && q < work + 2 * M) || (work >= q && work < q + M)) return BUB_EINVAL;
     for (size_t i = 0; i < b->slots.size(); ++i) {
@@ -1492,13 +1598,6 @@ int member_desc(const bub_batch::Member &m, BatchMember *d)
 }
 
 bool member_active(const bub_batch::Member &m) { return m.used && (m.open || m.remaining > 0); }
-
-// bub_batch_run takes the grouped launches below only when this is set.  They are switched off: on the
-// GPU a batch run through them once returned corrupted member states and once faulted the device, while
-// the same launches run block by block on the host reproduce every member bitwise; the cause, somewhere
-// in how the uploaded tables meet the launches that read them on the device, is not known yet.  Until it
-// is, bub_batch_run steps each member with its own kernels on the batch's lanes (as bub_batch_step).
-constexpr bool kGroupedLaunches = false;
 
 // Rewrite the member table and the launch lists for the members still stepping: both are filled in
 // the next staging buffer of the ring (once the upload that last read it has completed) and uploaded

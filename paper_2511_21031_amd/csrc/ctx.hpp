@@ -34,6 +34,8 @@ struct bub_ctx {
     int tile = 0;                // stage-kernel tile shape (index into the per-dimension list)
     int bin_groups = 0;          // stage-kernel workgroups per tile (0: chosen per launch from the tile count)
     int32_t *nsub_diag = nullptr;   // split-mode steps record their sub-step counts here ([2][nb][N])
+    bool src_on = false;         // one-way acoustic source set (bub_set_source)
+    bub_source src{};
     int prof_on = 0;
     size_t prof_used = 0;
     std::vector<ProfRec> prof;

@@ -24,7 +24,7 @@ struct Phys {
 };
 
 // Grid: cells per direction, boundary kind per direction (0 periodic,
-// 1 reflective; both ends equal), inverse spacing.
+// 1 reflective, 2 non-reflective; both ends equal), inverse spacing.
 struct Grid {
     int n[3];
     int bc[3];
@@ -50,7 +50,9 @@ struct Scalars {
     int err_code;             // sticky first error (0 = none)
     int err_bin;
     long long err_cell;
-    long long pad_[13];
+    double t;                 // time at the start of the current step (the stages' clock)
+    double t_next;            // time of the state after the last step (the context's clock)
+    long long pad_[11];
     // bit patterns of partial maxima of (|u_d| + c)/dx_d (positive doubles order as integers)
     unsigned long long wmax[WMAX_SLOTS * WMAX_STRIDE];
 };
@@ -78,7 +80,9 @@ __device__ inline void raise_error(Scalars *s, int code, long long cell, int bin
 
 // Ghost-cell map of one coordinate.  Periodic: wrap.  Reflective: fold with
 // period 2n (one mirror per wall crossing); `flip` toggles on every mirror so
-// the normal velocity of the ghost is negated.
+// the normal velocity of the ghost is negated.  Non-reflective (Sec. 5.1, after
+// Thompson): the boundary cell itself, so the Riemann problem at the boundary
+// face has no jump and no wave enters from outside.
 __host__ __device__ inline int map_coord(int i, int n, int bc, bool &flip)
 {
     if ((unsigned)i < (unsigned)n) return i;
@@ -86,6 +90,7 @@ __host__ __device__ inline int map_coord(int i, int n, int bc, bool &flip)
         int m = i % n;
         return m < 0 ? m + n : m;
     }
+    if (bc == 2) return i < 0 ? 0 : n - 1;   // non-reflective: the boundary cell's own state
     int p = 2 * n;
     int m = i % p;
     if (m < 0) m += p;

@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ prim, d
 }
 
 // Time step from the wave-speed max (or a fixed value); clears the partial maxima for the next
-// step.  One wave of WMAX_SLOTS threads.
+// step and advances the clock (t: this step's start, t_next: its end).  One wave of WMAX_SLOTS threads.
 __device__ __forceinline__ void dt_block(Scalars *sc, double fixed_dt, double cfl, double *user_dt)
 {
     const int i = threadIdx.x;
@@ -325,6 +325,8 @@ __device__ __forceinline__ void dt_block(Scalars *sc, double fixed_dt, double cf
         double dt = fixed_dt;
         if (!(dt > 0.0)) dt = cfl / __longlong_as_double((long long)m);
         sc->dt = dt;
+        sc->t = sc->t_next;        // the step starts where the last one ended
+        sc->t_next = sc->t + dt;
         if (user_dt) *user_dt = dt;
     }
 }
