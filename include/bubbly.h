@@ -157,6 +157,26 @@ int bub_rhs_stage(bub_ctx *ctx, const double *q, double *rhs, void *stream);
  * S_b(dt/2) S_f(dt) S_b(dt/2) (Strang splitting, Sec. 3). */
 int bub_rk3_step(bub_ctx *ctx, double *q, double *work, double dt, double *dt_dev, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): bub_rhs_stage without
+ * a context.  The problem is described as for bub_ctx_create; the context's device
+ * buffers (bin table, scalars, one primitive scratch of (ndim+6)*N doubles) live in
+ * one static device array of BUB_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends, and nothing is allocated (no hipMalloc, no host heap).  q (device,
+ * read) and rhs (device, written) are [nvar][N] as for bub_rhs_stage, and the
+ * result is bitwise that of bub_rhs_stage on a context of the same problem.  err
+ * (device int64[3], may be NULL) receives the device error word (code, first
+ * failing cell or -1, failing bin or -1) after the call's kernels.
+ * BUB_ENOMEM if the problem's buffers, 9984 + 8*(ndim+6)*N bytes, exceed the
+ * static array (2D grids up to 723^2 cells fit, 3D up to 77^3); the argument
+ * errors of bub_ctx_create and
+ * bub_rhs_stage.  Every call on one GPU uses that GPU's array: calls whose work
+ * overlaps on one GPU (other streams, other threads) race and must be ordered
+ * by the caller. */
+#define BUB_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int bub_rhs_stage_noalloc(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, const bub_bins *bins,
+                          const bub_opts *opts, const double *q, double *rhs, int64_t *err, void *stream);
+
 /* One-way planar acoustic source (Sec. 2: forcing of the mass, momentum and
  * energy equations on a source plane; the Sec. 5.1 set-ups are driven this
  * way).  The plane is normal to axis `dir` (< ndim) at coordinate x (cell i has

@@ -1560,6 +1560,78 @@ int bub_batch_autotune(bub_batch *b, int reps, int *classes, void *stream)
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// Right-hand side for callers that cannot allocate: the context lives on the host stack and its
+// device buffers (bin table, scalars, primitive scratch) in one file-scope device array
+// ---------------------------------------------------------------------------
+
+// Held by every GPU the library runs on until the process ends.  In host code `scratch` names a
+// host-side stand-in: only the address from hipGetSymbolAddress is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[BUB_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up once per device (with it current).
+int scratch_address(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return BUB_EHIP;
+    if (dev >= NOALLOC_MAX_DEVICES) return BUB_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return BUB_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return BUB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bub_rhs_stage_noalloc(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, const bub_bins *bins,
+                          const bub_opts *opts, const double *q, double *rhs, int64_t *err, void *stream)
+{
+    if (!q || !rhs || q == rhs) return BUB_EINVAL;
+    bub_ctx c;   // host side on the stack
+    int rc = ctx_fill(grid, liq, gas, bins, opts, &c);
+    if (rc) return rc;
+    // bin table | scalars | one primitive scratch (a right-hand side needs no second one)
+    size_t off_sc, off_P, off_P2, total;
+    ctx_buffer_layout(c.ndim, c.N, &off_sc, &off_P, &off_P2, &total);
+    const size_t need = off_P + sizeof(double) * (size_t)c.nprim * (size_t)c.N;
+    if (need > BUB_NOALLOC_SCRATCH_BYTES) return BUB_ENOMEM;
+    void *base_v = nullptr;
+    if ((rc = scratch_address(&base_v))) return rc;
+    char *base = (char *)base_v;
+    c.owns = false;
+    c.d_bins = (double *)base;
+    c.d_sc = (Scalars *)(base + off_sc);
+    c.d_P = (double *)(base + off_P);
+    c.d_P2 = nullptr;
+    ctx_finish(&c);
+    hipStream_t s = (hipStream_t)stream;
+    BinTable t{};
+    bin_table(&c, t.v);
+    // the previous call's contents are overwritten: bin table, cleared error word and maxima
+    hipLaunchKernelGGL(k_ctx_init, dim3(1), dim3(64), 0, s, c.d_bins, t, 3 * c.nb, c.d_sc);
+    HIP_OK(hipGetLastError());
+    if ((rc = rhs_stage_impl(&c, q, rhs, s))) return rc;
+    if (err) {
+        hipLaunchKernelGGL(k_err_copy, dim3(1), dim3(64), 0, s, c.d_sc, err);
+        HIP_OK(hipGetLastError());
+    }
+    return BUB_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
 // Batches, grouped form: one launch per phase and kernel class over a device member table
 // ---------------------------------------------------------------------------
 namespace {
