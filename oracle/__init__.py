@@ -315,7 +315,8 @@ def el_rhs(pb, ql, alpha, dalpha):
 
 
 def el_step(pb, ql, bub, alpha, dalpha, dt=0.0):
-    """One Strang-split Lagrangian step in place; returns (dt_used, accepted sub-steps per bubble)."""
+    """One Strang-split Lagrangian step in place (the clock pb.t advances); returns (dt_used, accepted
+    sub-steps per bubble)."""
     for a in (ql, bub, alpha, dalpha):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     ns = np.zeros(bub.shape[1], dtype=np.int32)
@@ -323,4 +324,5 @@ def el_step(pb, ql, bub, alpha, dalpha, dt=0.0):
     rc = lib().orc_el_step(ctypes.byref(pb), _ptr(ql), _ptr(bub), bub.shape[1], float(dt), _ptr(alpha),
                            _ptr(dalpha), ns.ctypes.data_as(_ip), ctypes.byref(used))
     _check(rc, "el_step")
+    pb.t += used.value
     return used.value, ns

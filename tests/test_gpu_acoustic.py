@@ -136,13 +136,15 @@ def test_pulse_leaves_through_nonreflective_ends(torch, bub, orc):
         ctx.rk3_step(q, work, dt)
         n += 1
     got = q.cpu().numpy()
+    m_scale = np.abs(case.prim[0] * case.prim[1]).max()          # the pulse's momentum at the start
     res_gpu = np.abs(_pressure(orc, pb, got)).max() / 1e3
     res_orc = np.abs(_pressure(orc, pb, q_ref)).max() / 1e3
     print(f"pulse out after {n} steps: residual GPU {res_gpu:.3e}, oracle {res_orc:.3e}")
     assert res_gpu < 1e-4
     # the residual is itself a rounding-level field (9 mPa where one ulp of E moves p by 0.4 uPa)
     assert abs(res_gpu - res_orc) < 1e-7
-    assert rel_err(got[1], q_ref[1]) < 1e-9
+    # what is left of the momentum is rounding-level too: compared against the pulse's own momentum
+    assert np.abs(got[1] - q_ref[1]).max() < 1e-7 * m_scale
 
 
 @pytest.mark.parametrize("kind", ["1d_plus", "1d_minus", "2d_y"])
@@ -174,3 +176,28 @@ def test_burst_trajectory_mixed_precision(torch, bub, orc):
     got, q_ref, _, dp, _, amp = _trajectory(torch, bub, orc, case, src, 150, precision=bub.PREC_MIXED)
     print(f"mixed, 150 steps: |dp'| {dp:.3e} Pa of amplitude {amp:.1f} Pa")
     assert dp < 0.02 * src["amp"]
+
+
+def test_isolated_bubble_follows_keller_miksis(torch, bub, orc):
+    """Sec. 5.1's isolated-bubble set-up on the GPU (split mode, the oracle's steps): the probe cell's
+    bubble radius follows Keller-Miksis driven by the emitted wave as the oracle's does, and agrees with
+    the oracle's radius to ten times the sub-step tolerance."""
+    from tests.test_oracle_acoustic_pins import km_driven_by_emission, run_isolated_bubble
+    case, src, probe = W.isolated_bubble(50, 0.2)
+    pb, ts, R_orc, dts = run_isolated_bubble(orc, case, src, probe)
+    ctx = bub.context_from_case(case, source=src, bubble_mode=bub.BUBBLES_SPLIT)
+    q = ctx.init_state(torch.from_numpy(case.prim).cuda())
+    work = ctx.new_work()
+    R = [case.r0_median]
+    for dt in dts:
+        ctx.rk3_step(q, work, dt)
+        n = ctx.moments(q)[0, probe]
+        R.append((q[4, probe] / n).item())
+    assert ctx.last_error()[0] == 0
+    R = np.array(R)
+    Rk = km_driven_by_emission(orc, pb, case, src, probe, ts)
+    rmse = np.sqrt(np.mean((R - Rk) ** 2)) / case.r0_median
+    dev = np.abs(R - R_orc).max() / case.r0_median
+    print(f"isolated bubble: RMSE/R0 against Keller-Miksis {rmse:.2e}, max |R_gpu - R_oracle|/R0 {dev:.2e}")
+    assert rmse < 5e-3
+    assert dev < 1e-3

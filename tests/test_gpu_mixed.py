@@ -152,3 +152,47 @@ def test_mixed_vs_fp64_full_3d_crop(torch, bub):
     e_R = float(np.abs(Rm - R64).max() / np.abs(R64).max())
     print(f"256^3 split, 3 steps, 64^3 crop: mixed vs FP64 p {e_p:.2e} p_l {e_pl:.2e} alpha {e_a:.2e} R {e_R:.2e}")
     assert max(e_p, e_pl, e_a) < TOL_P_ALPHA
+
+
+def test_full_3d_crop_against_oracle(torch, bub, orc):
+    """256^3, 21 bins, 10 atm pulse, split mode, 3 steps: the central 64^3 crop of the GPU state, FP64 and
+    mixed, against the FP64 oracle.  Each RK3 step reaches 3 stages x 3 cells = 9 cells, so the oracle runs
+    a 118^3 box around the crop (27 cells of margin) with the GPU's steps; its own boundaries cannot reach
+    the crop in 3 steps."""
+    import dataclasses
+    case = W.c3()
+    n, lo, m = 256, 96, 27
+    dts = []
+    out = {}
+    for prec in (bub.PREC_FP64, bub.PREC_MIXED):
+        ctx = bub.context_from_case(case, precision=prec, bubble_mode=bub.BUBBLES_SPLIT)
+        q = ctx.init_state(_gpu(torch, case.prim))
+        work = ctx.new_work()
+        dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+        for k in range(3):
+            if prec == bub.PREC_FP64:                   # CFL steps, recorded ...
+                ctx.rk3_step(q, work, 0.0, dt_dev)
+                dts.append(dt_dev.item())
+            else:                                       # ... and replayed by the mixed run and the oracle
+                ctx.rk3_step(q, work, dts[k])
+        assert ctx.last_error()[0] == 0
+        sl = slice(lo, lo + 64)
+        out[prec] = q.view(q.shape[0], n, n, n)[:, sl, sl, sl].cpu().numpy().reshape(q.shape[0], -1)
+        del q, work, ctx
+        torch.cuda.empty_cache()
+    nb_ = lo - m, lo + 64 + m
+    prim = case.prim.reshape(-1, n, n, n)[:, nb_[0]:nb_[1], nb_[0]:nb_[1], nb_[0]:nb_[1]]
+    s = nb_[1] - nb_[0]
+    box = dataclasses.replace(case, n=(s, s, s), prim=np.ascontiguousarray(prim.reshape(prim.shape[0], -1)))
+    pb = orc.problem_from_case(box, split=1)
+    q_ref = orc.init_state(pb, box.prim)
+    for dt in dts:
+        orc.rk3_step(pb, q_ref, dt)
+    ref = q_ref.reshape(-1, s, s, s)[:, m:m + 64, m:m + 64, m:m + 64].reshape(q_ref.shape[0], -1)
+    pc = orc.problem_from_case(dataclasses.replace(case, n=(64, 64, 64)), split=1)
+    errs = {p: _field_errors(orc, pc, np.ascontiguousarray(out[p]), np.ascontiguousarray(ref)) for p in out}
+    print(f"256^3 split, 3 steps, 64^3 crop against the oracle: FP64 {errs[bub.PREC_FP64]}, "
+          f"mixed {errs[bub.PREC_MIXED]}")
+    e64, emx = errs[bub.PREC_FP64], errs[bub.PREC_MIXED]
+    assert max(e64["p"], e64["alpha"], e64["R"]) < 1e-8
+    assert max(emx["p_l"], emx["p"], emx["alpha"]) < TOL_P_ALPHA

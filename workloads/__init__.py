@@ -324,7 +324,8 @@ def source_burst(axis: int, sign: int, x: float, dx: float, *, cells_per_wavelen
 
 
 def acoustic_tube(ndim: int = 1, n: int = 600, length: float = 0.15, nb: int = 1, *, alpha: float = 0.0,
-                  axis: int = 0, ncross: int = 4, bc=BC_NONREFLECTIVE, cfl: float = 0.3) -> Case:
+                  axis: int = 0, ncross: int = 4, bc=BC_NONREFLECTIVE, cfl: float = 0.3,
+                  r0_median: float = 10e-6) -> Case:
     """Water at rest with the given void fraction; `n` cells of length/n along `axis`, `ncross` periodic
     cells across it (2D and 3D); non-reflective ends along the axis."""
     dx = length / n
@@ -336,7 +337,19 @@ def acoustic_tube(ndim: int = 1, n: int = 600, length: float = 0.15, nb: int = 1
     fields = [np.full((1, 1, 1), w["rho0"])] + [np.zeros((1, 1, 1))] * ndim \
         + [np.full((1, 1, 1), w["p0"]), np.full((1, 1, 1), alpha)]
     bcs = tuple((bc, bc) if d == axis else (BC_PERIODIC, BC_PERIODIC) for d in range(3))
-    return Case("acoustic_tube", ndim, nn, (dx, dx, dx), bcs, nb, 10e-6, 0.3, cfl, 1, _pack(fields, nn))
+    return Case("acoustic_tube", ndim, nn, (dx, dx, dx), bcs, nb, r0_median, 0.3, cfl, 1, _pack(fields, nn))
+
+
+def isolated_bubble(cells_per_wavelength: float = 50.0, cfl: float = 0.2):
+    """The isolated-bubble validation set-up: a 50 um air bubble in water (one bin, trace void fraction so
+    the bubble does not act on the liquid), driven by one cycle of a 0.2 MPa, 150 kHz plane wave emitted at
+    a quarter of a four-wavelength tube with non-reflective ends; returns (case, source, probe cell)."""
+    f = 150e3
+    dx = c0_water() / f / cells_per_wavelength
+    n = int(round(4 * cells_per_wavelength))
+    case = acoustic_tube(1, n=n, length=n * dx, nb=1, alpha=1e-8, cfl=cfl, r0_median=50e-6)
+    src = source_burst(0, 1, 0.25 * n * dx, dx, cells_per_wavelength=cells_per_wavelength, amp=2e5, cycles=1.0)
+    return case, src, int(0.6 * n)
 
 
 def pulse_tube(n: int = 400, length: float = 0.1, *, amp: float = 1e3, x0_frac: float = 0.6,
