@@ -380,6 +380,11 @@ int bub_batch_info(const bub_batch *batch, int *ncases, int64_t *cells, int64_t 
  * Synchronises `stream`; results do not depend on the tile shape. */
 int bub_batch_autotune(bub_batch *batch, int reps, int *classes, void *stream);
 
+/* Tile-shape cache file of the class autotuner (NULL or "": none): a class
+ * found there takes the cached shape without timing, a class tuned here is
+ * appended (bub_autotune_cached). */
+int bub_batch_tune_cache(bub_batch *batch, const char *cache_path);
+
 /* Synchronises `stream`, then reports and clears the sticky device error word:
  * *code (BUB_OK or a device BUB_E* code), *cell (first failing cell or -1),
  * *bin (failing bin or -1).  Any output pointer may be NULL. */
@@ -422,6 +427,19 @@ int bub_bin_groups(bub_ctx *ctx, int groups);
  * each shape.  Synchronises `stream`. */
 int bub_autotune(bub_ctx *ctx, const double *q, double *scratch, int reps, double *ms_out, int *best,
                  void *stream);
+
+/* The autotuner with a cache of its choices that persists across processes:
+ * a text file (created on the first store) of lines
+ * "<arch> <ndim> <nb> <precision> <size class> <tile>", keyed by the GPU's
+ * architecture name (e.g. gfx950), the context's dimensionality, bin count
+ * and precision, and floor(log2 N).  With an entry for the context's key the
+ * context takes that tile shape at once (*hit = 1; no launch, no
+ * synchronisation, q and scratch unused); otherwise bub_autotune runs and its
+ * choice is appended to the file (*hit = 0).  Lines that do not parse or name
+ * no valid shape are ignored; the last matching line wins.  best and hit may
+ * be NULL.  BUB_EINVAL if the file cannot be appended to. */
+int bub_autotune_cached(bub_ctx *ctx, const char *cache_path, const double *q, double *scratch, int reps,
+                        int *best, int *hit, void *stream);
 
 /* Kernel timing for benchmarks.  bub_profile(ctx, 1) starts recording a HIP
  * event pair around every kernel the context launches afterwards (on the

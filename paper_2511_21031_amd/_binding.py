@@ -94,6 +94,9 @@ _SIGS = {
     "bub_bin_groups": [_vp, ctypes.c_int],
     "bub_substep_counts": [_vp, _vp],
     "bub_autotune": [_vp, _vp, _vp, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int), _vp],
+    "bub_autotune_cached": [_vp, ctypes.c_char_p, _vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                            ctypes.POINTER(ctypes.c_int), _vp],
+    "bub_batch_tune_cache": [_vp, ctypes.c_char_p],
     "bub_batch_create": [ctypes.c_int, ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_vp)],
     "bub_batch_destroy": [_vp],
     "bub_batch_add": [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
@@ -383,6 +386,17 @@ class Context:
                                   _stream(stream)), "bub_autotune")
         return best.value, list(ms)
 
+    def autotune_cached(self, cache_path: str, q: torch.Tensor, scratch: torch.Tensor | None = None, reps: int = 5,
+                        stream=None):
+        """Tile shape from the cache file if it holds this context's key, else tuned and stored;
+        returns (best index, whether the cache held it)."""
+        scratch = torch.empty_like(q) if scratch is None else scratch
+        best, hit = ctypes.c_int(), ctypes.c_int()
+        _check(lib().bub_autotune_cached(self._h, str(cache_path).encode(), _ptr(q), _ptr(scratch), int(reps),
+                                         ctypes.byref(best), ctypes.byref(hit), _stream(stream)),
+               "bub_autotune_cached")
+        return best.value, bool(hit.value)
+
     def profile(self, enable: bool):
         _check(lib().bub_profile(self._h, 1 if enable else 0), "bub_profile")
 
@@ -494,6 +508,11 @@ class Batch:
     def set_lanes(self, lanes: int):
         """Internal streams the members are dealt over (1..16)."""
         _check(lib().bub_batch_lanes(self._h, int(lanes)), "bub_batch_lanes")
+
+    def set_tune_cache(self, cache_path: str | None):
+        """Tile-shape cache file of the class autotuner (None: none)."""
+        _check(lib().bub_batch_tune_cache(self._h, str(cache_path).encode() if cache_path else None),
+               "bub_batch_tune_cache")
 
     def autotune(self, reps: int = 3, stream=None) -> int:
         """Tune the stage tile shape of every new (ndim, nb) class; returns the number of tuned classes."""

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <string>
 #include <type_traits>
 
 #include "bubbly.h"
@@ -1102,6 +1103,87 @@ int bub_tile_get(const bub_ctx *c, int *idx)
     return BUB_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Tile-shape cache: a text file of lines "<arch> <ndim> <nb> <precision> <size class> <tile>", the size
+// class being floor(log2 N).  Lines that do not parse, or name another shape count, are ignored; the
+// last matching line wins.
+struct TuneKey {
+    char arch[64];
+    int ndim, nb, precision, size_class;
+};
+
+int tune_key(const bub_ctx *c, TuneKey *k)
+{
+    hipDeviceProp_t prop{};
+    if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return BUB_EHIP;
+    std::memset(k->arch, 0, sizeof(k->arch));
+    for (int i = 0; i < (int)sizeof(k->arch) - 1 && prop.gcnArchName[i] && prop.gcnArchName[i] != ':' &&
+                    prop.gcnArchName[i] != ' ';
+         ++i)
+        k->arch[i] = prop.gcnArchName[i];
+    k->ndim = c->ndim;
+    k->nb = c->nb;
+    k->precision = c->opts.precision;
+    int sc = 0;
+    while ((1LL << (sc + 1)) <= c->N) ++sc;
+    k->size_class = sc;
+    return BUB_OK;
+}
+
+// The cached tile of key k in the file at path, or -1.
+int tune_lookup(const char *path, const TuneKey &k, int ntiles)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f) return -1;
+    char line[256];
+    int found = -1;
+    while (std::fgets(line, sizeof(line), f)) {
+        char arch[64];
+        int nd, nb, pr, sc, t;
+        if (std::sscanf(line, "%63s %d %d %d %d %d", arch, &nd, &nb, &pr, &sc, &t) != 6) continue;
+        if (std::strcmp(arch, k.arch) == 0 && nd == k.ndim && nb == k.nb && pr == k.precision &&
+            sc == k.size_class && t >= 0 && t < ntiles)
+            found = t;
+    }
+    std::fclose(f);
+    return found;
+}
+
+int tune_store(const char *path, const TuneKey &k, int tile)
+{
+    FILE *f = std::fopen(path, "a");   // one short line per append: whole lines even with concurrent writers
+    if (!f) return BUB_EINVAL;
+    const int ok = std::fprintf(f, "%s %d %d %d %d %d\n", k.arch, k.ndim, k.nb, k.precision, k.size_class, tile) > 0;
+    return std::fclose(f) == 0 && ok ? BUB_OK : BUB_EINVAL;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bub_autotune_cached(bub_ctx *c, const char *cache_path, const double *q, double *scratch, int reps, int *best,
+                        int *hit, void *stream)
+{
+    if (!c || !cache_path) return BUB_EINVAL;
+    TuneKey k;
+    int rc = tune_key(c, &k);
+    if (rc) return rc;
+    const int t = tune_lookup(cache_path, k, TILE_COUNT[c->ndim]);
+    if (hit) *hit = t >= 0;
+    if (t >= 0) {
+        c->tile = t;
+        if (best) *best = t;
+        return BUB_OK;
+    }
+    int tb = 0;
+    if ((rc = bub_autotune(c, q, scratch, reps, nullptr, &tb, stream))) return rc;
+    if (best) *best = tb;
+    return tune_store(cache_path, k, tb);
+}
+
 int bub_autotune(bub_ctx *c, const double *q, double *scratch, int reps, double *ms_out, int *best, void *stream)
 {
     if (!c || !q || !scratch || q == scratch || reps < 1) return BUB_EINVAL;
@@ -1234,6 +1316,7 @@ struct bub_batch {
     hipEvent_t join[NSTREAM] = {};
     std::vector<std::pair<int, int>> tuned_key;   // (ndim, nb) classes with an autotuned tile
     std::vector<int> tuned_tile;
+    std::string tune_cache;                       // tile-shape cache file of the class autotuner ("" = none)
 };
 
 namespace {
@@ -1532,6 +1615,13 @@ int bub_batch_lanes(bub_batch *b, int lanes)
     return BUB_OK;
 }
 
+int bub_batch_tune_cache(bub_batch *b, const char *cache_path)
+{
+    if (!b) return BUB_EINVAL;
+    b->tune_cache = cache_path ? cache_path : "";
+    return BUB_OK;
+}
+
 int bub_batch_autotune(bub_batch *b, int reps, int *classes, void *stream)
 {
     if (!b || reps < 1) return BUB_EINVAL;
@@ -1542,8 +1632,11 @@ int bub_batch_autotune(bub_batch *b, int reps, int *classes, void *stream)
         if (!m.used) continue;
         int t = batch_class_tile(b, m.ctx);
         if (t < 0) {
-            // time the stage kernel's tile shapes on this member (right-hand side into its work buffer)
-            int rc = bub_autotune(m.ctx, m.q, m.work, reps, nullptr, &t, s);
+            // the cached shape of this class, or time the stage kernel's tile shapes on this member
+            // (right-hand side into its work buffer)
+            int rc = b->tune_cache.empty()
+                         ? bub_autotune(m.ctx, m.q, m.work, reps, nullptr, &t, s)
+                         : bub_autotune_cached(m.ctx, b->tune_cache.c_str(), m.q, m.work, reps, &t, nullptr, s);
             if (rc) return rc;
             b->tuned_key.emplace_back(m.ctx->ndim, m.ctx->nb);
             b->tuned_tile.push_back(t);

@@ -72,7 +72,7 @@ class Server:
 
     def __init__(self, hbm_budget: int, max_slots: int = 64, precision=None, bubble_mode=None,
                  chunk: int = 10, keep_results: bool = False, autotune: bool = True, footprint=footprint_bytes,
-                 lanes: int = 4, use_run: bool = True):
+                 lanes: int = 4, use_run: bool = True, tune_cache: str | None = None):
         self.budget = int(hbm_budget)
         self.max_slots = int(max_slots)
         self.precision = precision
@@ -83,6 +83,7 @@ class Server:
         self.footprint = footprint
         self.lanes = int(lanes)
         self.use_run = bool(use_run)   # chunks through bub_batch_run (step counts) or bub_batch_step
+        self.tune_cache = tune_cache   # tile-shape cache file of the class autotuner (persists across runs)
         self.used = 0
         self.peak_used = 0
         self.peak_active = 0
@@ -102,6 +103,8 @@ class Server:
         self.stream = torch.cuda.Stream()
         self.batch = Batch(self.precision, self.max_slots, hbm_budget=self.budget)
         self.batch.set_lanes(self.lanes)
+        if self.tune_cache:
+            self.batch.set_tune_cache(self.tune_cache)
 
     def _admit(self, rec: Record, case) -> int:
         import torch

@@ -222,6 +222,44 @@ def test_stream_batch_class_autotune(torch, bub):
     batch.close()
 
 
+def test_autotune_cache_persists_choices(torch, bub, tmp_path):
+    """bub_autotune_cached: a miss tunes and appends one line keyed by (arch, ndim, nb, precision,
+    floor(log2 N)); a later context of the same key takes the stored shape without timing; lines that do
+    not parse or name no valid shape are ignored; the batch's class autotuner reads the same file."""
+    case = W.random_smooth(2, (70, 37), 1e-4, 5, seed=41)
+    path = tmp_path / "tiles.txt"
+    path.write_text("not an entry\ngfx950 2 5 0 11 99\n")
+    ctx = bub.context_from_case(case)
+    q = ctx.init_state(_gpu(torch, case.prim))
+    best, hit = ctx.autotune_cached(str(path), q, reps=2)
+    assert not hit and ctx.tile == best
+    lines = path.read_text().splitlines()
+    assert len(lines) == 3
+    arch, nd, nb, prec, sc, tile = lines[-1].split()
+    assert (int(nd), int(nb), int(prec), int(sc), int(tile)) == (2, 5, 0, 11, best)   # 70 x 37 = 2590 cells
+    # the same key again: the cached shape, no new line
+    path.write_text(path.read_text() + f"{arch} 2 5 0 11 {(best + 1) % len(ctx.tiles())}\n"
+                    + f"{arch} 2 5 0 11 {best}\n")                                      # the last match wins
+    ctx2 = bub.context_from_case(case)
+    ctx2.tile = (best + 2) % len(ctx2.tiles())
+    best2, hit2 = ctx2.autotune_cached(str(path), q)
+    assert hit2 and best2 == best and ctx2.tile == best
+    assert len(path.read_text().splitlines()) == 5
+    # another size class or precision is a miss
+    mixed = bub.context_from_case(case, precision=bub.PREC_MIXED)
+    _, hit3 = mixed.autotune_cached(str(path), q, reps=2)
+    assert not hit3 and len(path.read_text().splitlines()) == 6
+    # the batch's class autotuner takes the cached shape of a member's class
+    batch = bub.Batch(bub.PREC_FP64, max_cases=2)
+    batch.set_tune_cache(str(path))
+    ctx3, q3, w3 = _fresh(torch, bub, case, False, bub.PREC_FP64)
+    ctx3.tile = (best + 1) % len(ctx3.tiles())
+    batch.add(ctx3, q3, w3)
+    assert batch.autotune(reps=2) == 1
+    assert ctx3.tile == best and len(path.read_text().splitlines()) == 6
+    batch.close()
+
+
 def test_graph_replays_match_eager_steps(torch, bub):
     """Every replay of the captured member steps, with eager work and host syncs in between,
     matches a twin of each member stepped eagerly, bitwise."""
