@@ -295,6 +295,15 @@ def main():
             os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)   # read when HIP initialises
         serving(args)
         return
+    import torch
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        # a 1 GiB device copy (1 GiB read, 1 GiB written) whose FETCH_SIZE / WRITE_SIZE calibrate the counters
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "collapse3d":
         collapse3d(args)
         return
@@ -302,17 +311,8 @@ def main():
         lagrangian(args)
         return
 
-    import torch
     import workloads
     import paper_2511_21031_amd as bub
-
-    torch.cuda.set_device(0)
-    if args.calibrate_copy:
-        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB read, 1 GiB written
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     case = workloads.c2()
     N, nb = case.ncells, case.nb
     first = args.precision
@@ -407,7 +407,7 @@ def stage_run(bub, torch, case, precision, args) -> dict:
            "k_prim_avg_ms": prim_ms / max(prim_n, 1), "k_prim_launches": prim_n,
            "other_avg_ms": other_ms / max(other_n, 1), "other_launches": other_n,
            "tile": [tx, ty, tz, blk], "autotune_ms": [round(m, 4) for m in tile_ms], "nvar": ctx.nvar,
-           "kname": f"void bub::k_stage<2, {tx}, {ty}, {tz}, {blk}, {tf}, true>"}
+           "kname": f"void bub::k_stage<2, {tx}, {ty}, {tz}, {blk}, {tf}, true, true>"}
     print(f"[stage] {precision}: {res['ms_per_step']:.3f} ms per step, stage kernel {res['k_stage_avg_ms']:.3f} ms, "
           f"primitive pass {res['k_prim_avg_ms']:.3f} ms x {prim_n}", file=sys.stderr, flush=True)
     del q, work, ctx

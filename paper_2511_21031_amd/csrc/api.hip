@@ -123,16 +123,31 @@ void tile_info(int *tx, int *ty, int *tz, int *block)
     *block = Tile<D, V>::BLOCK;
 }
 
-template <int D, int S, int CELLS>
-void launch_prim_s(bub_ctx *c, const double *q, double *out, int mode, hipStream_t s)
+// The kernels take the polytropic power x^(3 kappa) in one of two compiled forms: the fifth-root
+// Newton form when 3 kappa is a whole number of fifths (air's 4.2, 3, 5, ...), the general
+// exp2(3 kappa log2 x) form otherwise.  The general form has only stage shape 0 and no fused epilogue.
+bool pw_fast(const bub_ctx *c) { return c->ph.pw_c > 0; }
+
+template <int D, int S, int CELLS, bool PW>
+void launch_prim_p(bub_ctx *c, const double *q, double *out, int mode, hipStream_t s)
 {
     const dim3 grid((unsigned)((c->g.N + CELLS - 1) / CELLS)), block(S * CELLS);
     if (mode == PRIM_CFL)
-        hipLaunchKernelGGL((k_prim<D, PRIM_CFL, S, CELLS>), grid, block, 0, s, q, out, c->g, c->ph, c->bt, c->d_sc);
+        hipLaunchKernelGGL((k_prim<D, PRIM_CFL, S, CELLS, PW>), grid, block, 0, s, q, out, c->g, c->ph, c->bt,
+                           c->d_sc);
     else if (mode == PRIM_MOMENTS)
-        hipLaunchKernelGGL((k_prim<D, PRIM_MOMENTS, S, CELLS>), grid, block, 0, s, q, out, c->g, c->ph, c->bt, c->d_sc);
+        hipLaunchKernelGGL((k_prim<D, PRIM_MOMENTS, S, CELLS, PW>), grid, block, 0, s, q, out, c->g, c->ph, c->bt,
+                           c->d_sc);
     else
-        hipLaunchKernelGGL((k_prim<D, PRIM_ONLY, S, CELLS>), grid, block, 0, s, q, out, c->g, c->ph, c->bt, c->d_sc);
+        hipLaunchKernelGGL((k_prim<D, PRIM_ONLY, S, CELLS, PW>), grid, block, 0, s, q, out, c->g, c->ph, c->bt,
+                           c->d_sc);
+}
+
+template <int D, int S, int CELLS>
+void launch_prim_s(bub_ctx *c, const double *q, double *out, int mode, hipStream_t s)
+{
+    if (pw_fast(c)) launch_prim_p<D, S, CELLS, true>(c, q, out, mode, s);
+    else launch_prim_p<D, S, CELLS, false>(c, q, out, mode, s);
 }
 
 template <int D>
@@ -181,13 +196,25 @@ int launch_stage_t(bub_ctx *c, StageArgs A, hipStream_t s)
     if (A.Pout && A.ngroups != 1) return BUB_EINVAL;   // the fused epilogue needs every bin of a cell
     A.nitems = A.ntiles * A.ngroups;
     A.nblk_per_xcd = (A.nitems + 7) / 8;
+    const dim3 grid(8 * A.nblk_per_xcd), block(TC::BLOCK);
+    if (!pw_fast(c)) {
+        if constexpr (V == 0) {
+            if (A.Pout) return BUB_EINVAL;   // (stage_fusable is false for the general power)
+            long pr = prof_begin(c, BUB_K_STAGE, s);
+            hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF, false, false>), grid, block, 0, s,
+                               A, c->g, c->ph, c->bt);
+            prof_end(c, pr, s);
+            return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
+        }
+        return BUB_EUNSUPPORTED;
+    }
     long pr = prof_begin(c, BUB_K_STAGE, s);
     if (A.Pout)
-        hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF, true>), dim3(8 * A.nblk_per_xcd),
-                           dim3(TC::BLOCK), 0, s, A, c->g, c->ph, c->bt);
+        hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF, true, true>), grid, block, 0, s, A,
+                           c->g, c->ph, c->bt);
     else
-        hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF, false>), dim3(8 * A.nblk_per_xcd),
-                           dim3(TC::BLOCK), 0, s, A, c->g, c->ph, c->bt);
+        hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF, false, true>), grid, block, 0, s, A,
+                           c->g, c->ph, c->bt);
     prof_end(c, pr, s);
     return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
 }
@@ -203,7 +230,8 @@ template <int D, int S, int CELLS>
 void launch_bubble_s(bub_ctx *c, const BubbleArgs &B, hipStream_t s)
 {
     const dim3 grid((unsigned)((c->g.N + CELLS - 1) / CELLS)), block(S * CELLS);
-    hipLaunchKernelGGL((k_bubble<D, S, CELLS>), grid, block, 0, s, B, c->g, c->ph, c->bt, c->d_sc);
+    if (pw_fast(c)) hipLaunchKernelGGL((k_bubble<D, S, CELLS, true>), grid, block, 0, s, B, c->g, c->ph, c->bt, c->d_sc);
+    else hipLaunchKernelGGL((k_bubble<D, S, CELLS, false>), grid, block, 0, s, B, c->g, c->ph, c->bt, c->d_sc);
 }
 
 template <int D>
@@ -249,7 +277,7 @@ int prim(bub_ctx *c, const double *q, double *out, int mode, hipStream_t s)
 
 int stage_kernel(bub_ctx *c, const StageArgs &A, hipStream_t s)
 {
-    const int v = c->tile;
+    const int v = pw_fast(c) ? c->tile : 0;
     switch (c->ndim) {
     case 1:
         if (v == 1) return launch_stage_v<1, 1>(c, A, s);
@@ -355,7 +383,7 @@ long long stage_tiles(const bub_ctx *c)
 bool stage_fusable(const bub_ctx *c)
 {
     // (a viscous or source pass after the stage changes the state the epilogue would describe)
-    if (!c->d_P2 || slots_for(c->N) != 1 || c->opts.viscous || c->src_on) return false;
+    if (!c->d_P2 || slots_for(c->N) != 1 || c->opts.viscous || c->src_on || !pw_fast(c)) return false;
     int groups = 0;
     bin_grouping(c, stage_tiles(c), &groups);
     return groups == 1;
@@ -505,6 +533,14 @@ int ctx_fill(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, co
     c->ph.mu4 = 4.0 * gas->mu;
     c->ph.p0 = liq->p0;
     c->ph.rho0 = liq->rho0;
+    // 3 kappa = n / 5 for a whole n (kappa = 1, 1.4, 5/3, ...): the fifth-root power
+    const double n5 = 5.0 * c->ph.kappa3;
+    const long long n = std::llround(n5);
+    c->ph.pw_c = c->ph.pw_d = 0;
+    if (n >= 1 && n <= 100 && std::fabs(n5 - (double)n) <= 1e-12 * (double)n) {
+        c->ph.pw_c = (int)((n + 4) / 5);
+        c->ph.pw_d = (int)(5 * c->ph.pw_c - n);
+    }
     for (int d = 0; d < 3; ++d) {
         c->g.n[d] = grid->n[d];
         c->g.bc[d] = d < grid->ndim ? grid->bc[d][0] : 0;
@@ -849,7 +885,8 @@ int el_bubbles(bub_ctx *c, const ElGrid &g, double *b, long long nb, double *for
     O.rtol = c->opts.sub_rtol > 0.0 ? c->opts.sub_rtol : 1e-4;
     O.max_substeps = c->opts.max_substeps > 0 ? c->opts.max_substeps : 10000;
     O.nsub = nsub;
-    hipLaunchKernelGGL(k_el_ode, dim3(blocks_for(nb)), dim3(256), 0, s, O, c->ph, c->d_sc);
+    if (pw_fast(c)) hipLaunchKernelGGL(k_el_ode<true>, dim3(blocks_for(nb)), dim3(256), 0, s, O, c->ph, c->d_sc);
+    else hipLaunchKernelGGL(k_el_ode<false>, dim3(blocks_for(nb)), dim3(256), 0, s, O, c->ph, c->d_sc);
     prof_end(c, pr, s);
     return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
 }
@@ -859,7 +896,9 @@ int el_stage(bub_ctx *c, const ElGrid &g, ElStageArgs A, hipStream_t s)
     long pr = prof_begin(c, BUB_K_STAGE, s);
     const int ntx = (g.n[0] + ELT_X - 1) / ELT_X, nty = (g.n[1] + ELT_Y - 1) / ELT_Y;
     const int ntz = (g.n[2] + ELT_Z - 1) / ELT_Z;
-    hipLaunchKernelGGL(k_el_stage, dim3((unsigned)ntx * nty * ntz), dim3(ELT_BLOCK), 0, s, A, g, c->ph, ntx, nty);
+    const int ntiles = ntx * nty * ntz, per_xcd = (ntiles + 7) / 8;
+    hipLaunchKernelGGL(k_el_stage, dim3(8u * (unsigned)per_xcd), dim3(ELT_BLOCK), 0, s, A, g, c->ph, ntx, nty, ntiles,
+                       per_xcd);
     prof_end(c, pr, s);
     return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
 }
@@ -1092,6 +1131,7 @@ int bub_tile_info(const bub_ctx *c, int idx, int *tx, int *ty, int *tz, int *blo
 int bub_tile_set(bub_ctx *c, int idx)
 {
     if (!c || idx < 0 || idx >= TILE_COUNT[c->ndim]) return BUB_EINVAL;
+    if (idx != 0 && !pw_fast(c)) return BUB_EUNSUPPORTED;
     c->tile = idx;
     return BUB_OK;
 }
@@ -1168,6 +1208,10 @@ int bub_autotune_cached(bub_ctx *c, const char *cache_path, const double *q, dou
                         int *hit, void *stream)
 {
     if (!c || !cache_path) return BUB_EINVAL;
+    if (!pw_fast(c)) {   // one stage shape: nothing to choose or to store
+        if (hit) *hit = 0;
+        return bub_autotune(c, q, scratch, reps, nullptr, best, stream);
+    }
     TuneKey k;
     int rc = tune_key(c, &k);
     if (rc) return rc;
@@ -1204,7 +1248,10 @@ int bub_autotune(bub_ctx *c, const double *q, double *scratch, int reps, double 
     c->prof_on = 0;
     double best_ms = 1e300;
     int best_v = keep;
-    for (int v = 0; v < TILE_COUNT[c->ndim] && rc == BUB_OK; ++v) {
+    const int nshape = pw_fast(c) ? TILE_COUNT[c->ndim] : 1;
+    if (ms_out)
+        for (int v = nshape; v < TILE_COUNT[c->ndim]; ++v) ms_out[v] = -1.0;
+    for (int v = 0; v < nshape && rc == BUB_OK; ++v) {
         c->tile = v;
         rc = stage_kernel(c, A, s);  // warm-up (code load)
         if (rc) break;
@@ -1495,7 +1542,7 @@ int bub_batch_add(bub_batch *b, bub_ctx *c, double *q, double *work, int steps, 
             b->h_flags[i] = 0;
             b->dirty = true;
             const int t = batch_class_tile(b, c);
-            if (t >= 0) c->tile = t;
+            if (t >= 0 && pw_fast(c)) c->tile = t;
             *slot = (int)i;
             return BUB_OK;
         }
@@ -1629,7 +1676,7 @@ int bub_batch_autotune(bub_batch *b, int reps, int *classes, void *stream)
     int tuned = 0;
     for (size_t i = 0; i < b->slots.size(); ++i) {
         auto &m = b->slots[i];
-        if (!m.used) continue;
+        if (!m.used || !pw_fast(m.ctx)) continue;   // the general power has one stage shape
         int t = batch_class_tile(b, m.ctx);
         if (t < 0) {
             // the cached shape of this class, or time the stage kernel's tile shapes on this member
@@ -1737,6 +1784,7 @@ int cells_for(int S) { return S == 1 ? PRIM_CELLS_1 : PRIM_CELLS_S; }
 int member_desc(const bub_batch::Member &m, BatchMember *d)
 {
     const bub_ctx *c = m.ctx;
+    if (!pw_fast(c)) return BUB_EUNSUPPORTED;   // the grouped kernels carry the fifth-root power only
     *d = BatchMember{};
     const size_t M = (size_t)c->nvar * (size_t)c->N;
     d->q = m.q;

@@ -44,6 +44,7 @@ struct BinSums {
 // One bin's terms added to the sums.  Shared by the primitive pass and the epilogue of the fused
 // stage kernel, with its operation order fixed (explicit fused multiply-adds, no contraction), so both
 // give bitwise the same primitives.  C: the power's constant table (PPOW_TABLE, in LDS).
+template <bool PW>
 __device__ __forceinline__ void bin_add(BinSums &r, int i, double x, double y, double w, double pg0, double r0,
                                         int nb, const Phys &ph, const double *__restrict__ C)
 {
@@ -55,10 +56,10 @@ __device__ __forceinline__ void bin_add(BinSums &r, int i, double x, double y, d
     r.s2 = fma(w, x2, r.s2);
     r.s21 = fma(wx2, y, r.s21);
     r.s32 = fma(wx3 * y, y, r.s32);
-    r.sp = fma(wx3 * pg0, ppow(r0 * frcp(x), ph.kappa3, C), r.sp);
+    r.sp = fma(wx3 * pg0, kpow<PW>(r0 * frcp(x), ph, C), r.sp);
 }
 
-template <int D>
+template <int D, bool PW>
 __device__ __forceinline__ BinSums bin_sums(const double *__restrict__ q, const Phys &ph, const Bins &bins,
                                             long long N, long long c, int first, int stride,
                                             const double *__restrict__ C)
@@ -81,12 +82,12 @@ __device__ __forceinline__ BinSums bin_sums(const double *__restrict__ q, const 
         for (int u = 0; u < 4; ++u) {
             __builtin_amdgcn_sched_barrier(0);
             const int k = i + u * stride;
-            bin_add(r, k, x[u], y[u], bins.w[k], bins.pg0[k], bins.r0[k], nb, ph, C);
+            bin_add<PW>(r, k, x[u], y[u], bins.w[k], bins.pg0[k], bins.r0[k], nb, ph, C);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
     for (; i < nb; i += stride)
-        bin_add(r, i, q[(iNR + i) * N + c], q[(iNV + i) * N + c], bins.w[i], bins.pg0[i], bins.r0[i], nb, ph, C);
+        bin_add<PW>(r, i, q[(iNR + i) * N + c], q[(iNV + i) * N + c], bins.w[i], bins.pg0[i], bins.r0[i], nb, ph, C);
     return r;
 }
 
@@ -210,7 +211,7 @@ __device__ inline void cfl_reduce(double wmax, Scalars *sc) { wmax_post(wmax, sc
 // grids, which fill the chip on cells alone).
 // Block `blk` of the pass (cells blk*CELLS ..); every thread of the workgroup calls it.  s_pp: the
 // power's constant table in LDS, filled by the caller before a barrier.
-template <int D, int MODE, int S, int CELLS>
+template <int D, int MODE, int S, int CELLS, bool PW>
 __device__ __forceinline__ void prim_block(const double *__restrict__ q, double *__restrict__ out, const Grid &g,
                                            const Phys &ph, const Bins &bins, Scalars *sc, long long blk,
                                            const double *__restrict__ s_pp)
@@ -224,7 +225,7 @@ __device__ __forceinline__ void prim_block(const double *__restrict__ q, double 
     if constexpr (S == 1) {
         BinSums p;
         p.bad = bins.nb;
-        if (live && q[(D + 2) * N + c] > 0.0) p = bin_sums<D>(q, ph, bins, N, c, 0, 1, s_pp);
+        if (live && q[(D + 2) * N + c] > 0.0) p = bin_sums<D, PW>(q, ph, bins, N, c, 0, 1, s_pp);
         if (live) wmax = prim_finish<D, MODE>(q, out, g, ph, bins, sc, c, p);
     } else {
         __shared__ double s_sum[5][S][CELLS];
@@ -234,7 +235,7 @@ __device__ __forceinline__ void prim_block(const double *__restrict__ q, double 
         __syncthreads();
         BinSums p;
         p.bad = bins.nb;
-        if (live && q[(D + 2) * N + c] > 0.0) p = bin_sums<D>(q, ph, bins, N, c, slot, S, s_pp);
+        if (live && q[(D + 2) * N + c] > 0.0) p = bin_sums<D, PW>(q, ph, bins, N, c, slot, S, s_pp);
         s_sum[0][slot][cl] = p.s3;
         s_sum[1][slot][cl] = p.s2;
         s_sum[2][slot][cl] = p.s21;
@@ -262,14 +263,14 @@ __device__ __forceinline__ void prim_block(const double *__restrict__ q, double 
     if (MODE == PRIM_CFL) cfl_reduce(wmax, sc);
 }
 
-template <int D, int MODE, int S, int CELLS>
+template <int D, int MODE, int S, int CELLS, bool PW>
 __global__ void __launch_bounds__(S * CELLS) k_prim(const double *__restrict__ q, double *__restrict__ out,
                                                     Grid g, Phys ph, Bins bins, Scalars *sc)
 {
     __shared__ double s_pp[PPOW_N];   // constants of the polytropic power
     if (threadIdx.x < PPOW_N) s_pp[threadIdx.x] = PPOW_TABLE[threadIdx.x];
     __syncthreads();
-    prim_block<D, MODE, S, CELLS>(q, out, g, ph, bins, sc, blockIdx.x, s_pp);
+    prim_block<D, MODE, S, CELLS, PW>(q, out, g, ph, bins, sc, blockIdx.x, s_pp);
 }
 
 // Threads per cell for a grid of N cells: enough to give about 2^19 threads, at most PRIM_SLOTS.

@@ -9,9 +9,10 @@
 //                Dormand--Prince 5(4) sub-steps, forcing frozen.
 //  k_el_scatter  one wavefront per bubble: volume and volume rate smeared with
 //                the kernel (eq. kernel3D) by FP64 atomic adds.
-//  k_el_stage    a workgroup per tile of cells: WENO5 + HLLC fluxes of the
-//                liquid (stiffened gas), each face once, through LDS; the
-//                bubble source terms with alpha and its rate frozen; RK combine.
+//  k_el_stage    a workgroup per tile of cells: the tile's primitives and their
+//                halos staged in LDS per direction, WENO5 + HLLC fluxes of the
+//                liquid (stiffened gas), each face once; the bubble source
+//                terms with alpha and its rate frozen; RK combine.
 #pragma once
 
 #include <type_traits>
@@ -165,6 +166,7 @@ __global__ void __launch_bounds__(256) k_el_gather(const double *__restrict__ P,
 }
 
 // Dormand--Prince 5(4) step of (R, Rdot) (published tableau, 1980).
+template <bool PW>
 __device__ inline void dp54(const Phys &ph, double r0, double pg0, double pinf, double irho, double ic, double y0,
                             double y1, double h, double &r5, double &v5, double &r4, double &v4)
 {
@@ -177,7 +179,7 @@ __device__ inline void dp54(const Phys &ph, double r0, double pg0, double pinf, 
     const double b1 = 35.0 / 384.0, b3 = 500.0 / 1113.0, b4 = 125.0 / 192.0, b5 = -2187.0 / 6784.0, b6 = 11.0 / 84.0;
     const double e1 = 5179.0 / 57600.0, e3 = 7571.0 / 16695.0, e4 = 393.0 / 640.0, e5 = -92097.0 / 339200.0,
                  e6 = 187.0 / 2100.0, e7 = 1.0 / 40.0;
-    auto f = [&](double R, double V) { return km_rddot(ph, R, V, r0, pg0, pinf, irho, ic); };
+    auto f = [&](double R, double V) { return km_rddot<PW>(ph, R, V, r0, pg0, pinf, irho, ic); };
     double k1r = y1, k1v = f(y0, y1);
     double t0 = y0 + h * a21 * k1r, t1 = y1 + h * a21 * k1v;
     double k2r = t1, k2v = f(t0, t1);
@@ -211,6 +213,7 @@ struct ElOdeArgs {
     int *nsub;              // accumulated accepted sub-steps per bubble, or null
 };
 
+template <bool PW>
 __global__ void __launch_bounds__(256) k_el_ode(ElOdeArgs A, Phys ph, Scalars *sc)
 {
     const long long nb = A.nb;
@@ -233,7 +236,7 @@ __global__ void __launch_bounds__(256) k_el_ode(ElOdeArgs A, Phys ph, Scalars *s
             ++att;
             double hs = h < tau - t ? h : tau - t;
             double r5, v5, r4, v4;
-            dp54(ph, r0, pg0, pinf, irho, ic, y0, y1, hs, r5, v5, r4, v4);
+            dp54<PW>(ph, r0, pg0, pinf, irho, ic, y0, y1, hs, r5, v5, r4, v4);
             double err = dmax(fabs(r5 - r4) / fabs(r5), fabs(v5 - v4) / dmax(fabs(v5), vfloor));
             if (!(err == err)) err = INFINITY;
             if (err <= A.rtol && r5 > 0.0) {
@@ -305,21 +308,13 @@ struct ElStageArgs {
     int rhs_mode;
 };
 
-// Liquid face between cell (c - e_d) and c: HLLC flux and face-state pressures / normal velocities.
+// Liquid face between cell (c - e_d) and c from its six-cell stencil st[o][v] (cells c - 3 + o along d,
+// primitives rho, u, v, w, p; mirrored ghosts already carry the negated normal velocity): HLLC flux and the
+// face-state pressures and normal velocities.
 template <int d>
-__device__ inline void el_face(const double *__restrict__ P, const ElGrid &g, const Phys &ph, const int co[3],
-                               double F[5], double &pL, double &pR, double &uL, double &uR)
+__device__ inline void el_face_flux(const double (&st)[6][5], const Phys &ph, double F[5], double &pL, double &pR,
+                                    double &uL, double &uR)
 {
-    const long long N = g.N;
-    double st[6][5];
-    for (int o = 0; o < 6; ++o) {
-        int cc[3] = {co[0], co[1], co[2]};
-        bool flip = false;
-        cc[d] = map_coord(co[d] - 3 + o, g.n[d], g.bc[d], flip);
-        long long c = cc[0] + (long long)g.n[0] * (cc[1] + (long long)g.n[1] * cc[2]);
-        for (int v = 0; v < 5; ++v) st[o][v] = P[v * N + c];
-        if (flip) st[o][1 + d] = -st[o][1 + d];
-    }
     double WL[5], WR[5];
     for (int v = 0; v < 5; ++v) {
         WL[v] = weno5(st[0][v], st[1][v], st[2][v], st[3][v], st[4][v]);
@@ -360,17 +355,35 @@ __device__ inline void el_face(const double *__restrict__ P, const ElGrid &g, co
 }
 
 // Tile of the liquid stage: TX x TY x TZ cells, one thread per cell, every face of the tile computed
-// once (the faces of direction d form the box T + e_d; at most one per thread in each direction).
+// once (the faces of direction d form the box T + e_d; at most one per thread in each direction).  For
+// each direction the tile's cells and their 3-cell halos along it are first staged in LDS as a "line"
+// array (extent T_d + 6 along d), so every face reads its six-cell stencil there at a constant stride;
+// mirrored ghosts are stored with the normal velocity negated.
 constexpr int ELT_X = 8, ELT_Y = 8, ELT_Z = 3, ELT_BLOCK = 256;
 
-__global__ void __launch_bounds__(ELT_BLOCK) k_el_stage(ElStageArgs A, ElGrid g, Phys ph, int ntx, int nty)
+// Index in the line array of direction d of local cell (i, j, k), coordinate d in [-3, T_d + 3).
+template <int d>
+__device__ __forceinline__ int el_lidx(int i, int j, int k)
+{
+    if (d == 0) return (k * ELT_Y + j) * (ELT_X + 6) + (i + 3);
+    if (d == 1) return (k * (ELT_Y + 6) + (j + 3)) * ELT_X + i;
+    return ((k + 3) * ELT_Y + j) * ELT_X + i;
+}
+
+__global__ void __launch_bounds__(ELT_BLOCK) k_el_stage(ElStageArgs A, ElGrid g, Phys ph, int ntx, int nty, int ntiles,
+                                                        int per_xcd)
 {
     constexpr int TX = ELT_X, TY = ELT_Y, TZ = ELT_Z, T = TX * TY * TZ;
     constexpr int FMAX = TX * TY * (TZ + 1) > (TX + 1) * TY * TZ ? TX * TY * (TZ + 1) : (TX + 1) * TY * TZ;
-    __shared__ double s_f[9][FMAX];   // per face: flux[5], p_L, p_R, u_L, u_R
+    constexpr int LMAX = TX * TY * (TZ + 6) > (TX + 6) * TY * TZ ? TX * TY * (TZ + 6) : (TX + 6) * TY * TZ;
+    __shared__ double s_f[9][FMAX];    // per face: flux[5], p_L, p_R, u_L, u_R
+    __shared__ double s_l[5][LMAX];    // line array of the current direction: rho, u, v, w, p
     const long long N = g.N;
     const int tid = threadIdx.x;
-    const int tile = blockIdx.x;
+    // XCD-aware order: blocks are dealt round-robin over the 8 XCDs, so block b takes tile
+    // (b mod 8) per_xcd + b / 8 and neighbouring tiles (which share halos) share an XCD's L2
+    const int tile = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+    if (tile >= ntiles) return;
     const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
     const int li = tid % TX, lj = (tid / TX) % TY, lk = tid / (TX * TY);
     const int co[3] = {x0 + li, y0 + lj, z0 + lk};
@@ -380,15 +393,39 @@ __global__ void __launch_bounds__(ELT_BLOCK) k_el_stage(ElStageArgs A, ElGrid g,
     double L[5] = {0, 0, 0, 0, 0}, gradp[3] = {0, 0, 0}, divpu = 0.0;
     auto dir = [&](auto dtag) {
         constexpr int d = decltype(dtag)::value;
+        constexpr int EX = TX + 6 * (d == 0), EY = TY + 6 * (d == 1), EZ = TZ + 6 * (d == 2), LD = EX * EY * EZ;
+        constexpr int STRIDE = d == 0 ? 1 : (d == 1 ? TX : TX * TY);
+        // stage the tile and its halos along d (every coordinate through the ghost map; only the
+        // mirror along d flips a velocity, the only one the faces of d read across a wall)
+        for (int e = tid; e < LD; e += ELT_BLOCK) {
+            const int i = e % EX - 3 * (d == 0), j = (e / EX) % EY - 3 * (d == 1), k = e / (EX * EY) - 3 * (d == 2);
+            bool fl[3] = {false, false, false};
+            const int gx = map_coord(x0 + i, g.n[0], g.bc[0], fl[0]);
+            const int gy = map_coord(y0 + j, g.n[1], g.bc[1], fl[1]);
+            const int gz = map_coord(z0 + k, g.n[2], g.bc[2], fl[2]);
+            const long long gc = (long long)gx + (long long)g.n[0] * ((long long)gy + (long long)g.n[1] * gz);
+            const int li_ = el_lidx<d>(i, j, k);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) s_l[v][li_] = A.P[v * N + gc];
+            if (fl[d]) s_l[1 + d][li_] = -s_l[1 + d][li_];
+        }
+        __syncthreads();
         constexpr int BX = TX + (d == 0), BY = TY + (d == 1), BZ = TZ + (d == 2), FD = BX * BY * BZ;
         for (int t = tid; t < FD; t += ELT_BLOCK) {
-            const int f[3] = {x0 + t % BX, y0 + (t / BX) % BY, z0 + t / (BX * BY)};
+            const int fi = t % BX, fj = (t / BX) % BY, fk = t / (BX * BY);
+            const int f[3] = {x0 + fi, y0 + fj, z0 + fk};
             // faces of cells outside the grid are not needed (the face at n[d] closes the last cell)
             bool need = true;
             for (int e = 0; e < 3; ++e) need = need && (e == d ? f[e] <= g.n[e] : f[e] < g.n[e]);
             if (!need) continue;
+            const int b0 = el_lidx<d>(fi - 3 * (d == 0), fj - 3 * (d == 1), fk - 3 * (d == 2));
+            double st[6][5];
+#pragma unroll
+            for (int o = 0; o < 6; ++o)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) st[o][v] = s_l[v][b0 + o * STRIDE];
             double F[5], pl, pr, ul, ur;
-            el_face<d>(A.P, g, ph, f, F, pl, pr, ul, ur);
+            el_face_flux<d>(st, ph, F, pl, pr, ul, ur);
             for (int k = 0; k < 5; ++k) s_f[k][t] = F[k];
             s_f[5][t] = pl;
             s_f[6][t] = pr;
@@ -406,7 +443,7 @@ __global__ void __launch_bounds__(ELT_BLOCK) k_el_stage(ElStageArgs A, ElGrid g,
             gradp[d] = (0.5 * (pl1 + pr1) - 0.5 * (pl0 + pr0)) * g.inv_dx;
             divpu += (0.5 * (pl1 * ul1 + pr1 * ur1) - 0.5 * (pl0 * ul0 + pr0 * ur0)) * g.inv_dx;
         }
-        __syncthreads();   // s_f is rewritten by the next direction
+        __syncthreads();   // s_l and s_f are rewritten by the next direction
     };
     dir(std::integral_constant<int, 0>{});
     dir(std::integral_constant<int, 1>{});

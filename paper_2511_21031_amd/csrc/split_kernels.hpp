@@ -27,6 +27,7 @@ struct BubbleArgs {
 
 // Adaptive integration of one bin over tau: (y0, y1) = (R, Rdot) in, advanced values out.
 // Returns the accepted sub-steps; raises E_SUBSTEP when the attempt budget runs out.
+template <bool PW>
 __device__ inline int bubble_bin(const Phys &ph, double &y0, double &y1, double r0, double pg0, double pl,
                                  double irhol, double ic, double tau, double rtol, double vfloor, int max_substeps,
                                  Scalars *sc, long long c, int i)
@@ -40,12 +41,12 @@ __device__ inline int bubble_bin(const Phys &ph, double &y0, double &y1, double 
         }
         ++attempts;
         if (h > tau - t) h = tau - t;
-        double k1r = y1, k1v = km_rddot(ph, y0, y1, r0, pg0, pl, irhol, ic);
+        double k1r = y1, k1v = km_rddot<PW>(ph, y0, y1, r0, pg0, pl, irhol, ic);
         double a0 = y0 + h * k1r, a1 = y1 + h * k1v;
-        double k2r = a1, k2v = km_rddot(ph, a0, a1, r0, pg0, pl, irhol, ic);
+        double k2r = a1, k2v = km_rddot<PW>(ph, a0, a1, r0, pg0, pl, irhol, ic);
         double b0 = 0.75 * y0 + 0.25 * (a0 + h * k2r), b1 = 0.75 * y1 + 0.25 * (a1 + h * k2v);
         double e0 = y0 + 0.5 * h * (k1r + k2r), e1 = y1 + 0.5 * h * (k1v + k2v);
-        double k3r = b1, k3v = km_rddot(ph, b0, b1, r0, pg0, pl, irhol, ic);
+        double k3r = b1, k3v = km_rddot<PW>(ph, b0, b1, r0, pg0, pl, irhol, ic);
         double n0 = y0 * (1.0 / 3.0) + (2.0 / 3.0) * (b0 + h * k3r);
         double n1 = y1 * (1.0 / 3.0) + (2.0 / 3.0) * (b1 + h * k3v);
         double err = dmax(fabs(n0 - e0) / fabs(n0), fabs(n1 - e1) / dmax(fabs(n1), vfloor));
@@ -70,7 +71,7 @@ __device__ inline int bubble_bin(const Phys &ph, double &y0, double &y1, double 
 // of sum w R^3 before and after, and bumps the cell's LDS counter; the slot that arrives last
 // updates alpha, so waves whose bins need fewer sub-steps leave without waiting.
 // Block `blk` of the half-step (cells blk*CELLS ..); every thread of the workgroup calls it.
-template <int D, int S, int CELLS>
+template <int D, int S, int CELLS, bool PW>
 __device__ __forceinline__ void bubble_block(const BubbleArgs &A, const Grid &g, const Phys &ph, const Bins &bins,
                                              Scalars *sc, long long blk)
 {
@@ -133,7 +134,7 @@ __device__ __forceinline__ void bubble_block(const BubbleArgs &A, const Grid &g,
             double y1 = q[(iNV + i) * N + c] * in;
             const double wi = bins.w[i];
             m3_old += wi * y0 * y0 * y0;
-            int acc = bubble_bin(ph, y0, y1, bins.r0[i], bins.pg0[i], pl, irhol, ic, tau, A.rtol, vfloor,
+            int acc = bubble_bin<PW>(ph, y0, y1, bins.r0[i], bins.pg0[i], pl, irhol, ic, tau, A.rtol, vfloor,
                                  A.max_substeps, sc, c, i);
             q[(iNR + i) * N + c] = n * y0;
             q[(iNV + i) * N + c] = n * y1;
@@ -163,10 +164,10 @@ __device__ __forceinline__ void bubble_block(const BubbleArgs &A, const Grid &g,
     }
 }
 
-template <int D, int S, int CELLS>
+template <int D, int S, int CELLS, bool PW>
 __global__ void __launch_bounds__(S * CELLS) k_bubble(BubbleArgs A, Grid g, Phys ph, Bins bins, Scalars *sc)
 {
-    bubble_block<D, S, CELLS>(A, g, ph, bins, sc, blockIdx.x);
+    bubble_block<D, S, CELLS, PW>(A, g, ph, bins, sc, blockIdx.x);
 }
 
 }  // namespace bub

@@ -138,7 +138,7 @@ struct StageLds {
 
 // The work of one tile (every thread of the workgroup calls it).  FUSE: the epilogue carries the
 // primitive pass of the state it writes (A.Pout, A.cfl).
-template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF, bool FUSE>
+template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF, bool FUSE, bool PW>
 // Bins b0 <= ib < b1 are this workgroup's; core_out: it also writes the mixture variables
 // (exactly one workgroup per tile does).
 __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, const Phys &ph, const Bins &bins,
@@ -479,7 +479,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
                 // Keller--Miksis in FP64 from the FP64 state of the owned cell
                 double own_R = xr0 * own_in, own_V = xv0 * own_in;
                 LR += own_n * own_V;
-                LV += own_n * km_rddot_t(ph, own_R, own_V, r0, pg0, own_pl, own_irhol, own_ic, s_pp);
+                LV += own_n * km_rddot_t<PW>(ph, own_R, own_V, r0, pg0, own_pl, own_irhol, own_ic, s_pp);
             }
             double xr = LR, xv = LV;
             if (!A.rhs_mode) {
@@ -490,7 +490,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
                     xv += A.a * own_nv;
                 }
             }
-            if constexpr (fuse) bin_add(acc, ib, xr, xv, bins.w[ib], pg0, r0, nb, ph, s_pp);
+            if constexpr (fuse) bin_add<PW>(acc, ib, xr, xv, bins.w[ib], pg0, r0, nb, ph, s_pp);
             if constexpr (DEFER) {
                 s_out[tid] = xr;
                 s_out[BLOCK + tid] = xv;
@@ -534,7 +534,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
     if (threadIdx.x < PPOW_N) s_pp[threadIdx.x] = PPOW_TABLE[threadIdx.x]; /* read after the tile's barriers */
 
 // Work item `item` (a tile, or one bin group of a tile) of a stage.
-template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF, bool FUSE>
+template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF, bool FUSE, bool PW>
 __device__ __forceinline__ void stage_item(const StageArgs &A, const Grid &g, const Phys &ph, const Bins &bins,
                                            int item, TF *__restrict__ s_coef, TF *__restrict__ s_scr,
                                            unsigned char *__restrict__ s_flag, double *__restrict__ s_out,
@@ -542,11 +542,11 @@ __device__ __forceinline__ void stage_item(const StageArgs &A, const Grid &g, co
 {
     const int tile = item / A.ngroups, grp = item - tile * A.ngroups;
     const int b0 = grp * A.bpg, b1 = b0 + A.bpg < bins.nb ? b0 + A.bpg : bins.nb;
-    stage_tile<D, TX_, TY_, TZ_, BLOCK, TF, FUSE>(A, g, ph, bins, tile, b0, b1, grp == 0, s_coef, s_scr, s_flag, s_out,
-                                                  s_pp);
+    stage_tile<D, TX_, TY_, TZ_, BLOCK, TF, FUSE, PW>(A, g, ph, bins, tile, b0, b1, grp == 0, s_coef, s_scr, s_flag,
+                                                      s_out, s_pp);
 }
 
-template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF, bool FUSE>
+template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF, bool FUSE, bool PW>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((D <= 2 && sizeof(TF) == 4 && !FUSE) ? 5 : 1))) k_stage(StageArgs A, Grid g, Phys ph, Bins bins)
 {
     BUB_STAGE_SHARED(D, TX_, TY_, TZ_, BLOCK, TF)
@@ -555,7 +555,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((D <
     const int b = blockIdx.x;
     const int item = (b & 7) * A.nblk_per_xcd + (b >> 3);
     if (item >= A.nitems) return;
-    stage_item<D, TX_, TY_, TZ_, BLOCK, TF, FUSE>(A, g, ph, bins, item, s_coef, s_scr, s_flag, s_out, s_pp);
+    stage_item<D, TX_, TY_, TZ_, BLOCK, TF, FUSE, PW>(A, g, ph, bins, item, s_coef, s_scr, s_flag, s_out, s_pp);
 }
 
 }  // namespace bub
