@@ -47,6 +47,9 @@ class Problem(ctypes.Structure):
         ("t", ctypes.c_double), ("src_on", ctypes.c_int), ("src_dir", ctypes.c_int), ("src_sign", ctypes.c_int),
         ("src_x", ctypes.c_double), ("src_width", ctypes.c_double), ("src_amp", ctypes.c_double),
         ("src_freq", ctypes.c_double), ("src_t0", ctypes.c_double), ("src_ncyc", ctypes.c_double),
+        ("contents", ctypes.c_int), ("gam_b", ctypes.c_double), ("Rg", ctypes.c_double), ("Rv", ctypes.c_double),
+        ("T0", ctypes.c_double), ("k_b", ctypes.c_double), ("D_v", ctypes.c_double),
+        ("beta_T", ctypes.c_double), ("beta_c", ctypes.c_double),
     ]
 
 
@@ -69,6 +72,10 @@ def lib():
         L.orc_bubble_advance.argtypes = [P, _dp, ctypes.c_double, _ip]
         L.orc_km_rddot.argtypes = [P] + [ctypes.c_double] * 7
         L.orc_km_rddot.restype = ctypes.c_double
+        L.orc_km_rddot_pb.argtypes = [P] + [ctypes.c_double] * 7
+        L.orc_km_rddot_pb.restype = ctypes.c_double
+        L.orc_contents_rates.argtypes = [P] + [ctypes.c_double] * 5 + [_dp, _dp]
+        L.orc_contents_rates.restype = None
         L.orc_weno5.argtypes = [_dp]
         L.orc_weno5.restype = ctypes.c_double
         L.orc_hllc.argtypes = [P, ctypes.c_int, _dp, _dp, _dp]
@@ -105,8 +112,10 @@ def _check(rc, what):
 
 
 def problem(ndim, n, dx, bc, nb, r0_median=10e-6, sigma_ln=0.3, cfl=0.3, liquid=None, gas=None,
-            split=0, sub_rtol=1e-4, max_substeps=10000, viscous=0, source=None, t=0.0) -> Problem:
-    """source: dict(dir, sign, x, width, amp, freq, t0=0, ncyc=0) of the one-way acoustic source."""
+            split=0, sub_rtol=1e-4, max_substeps=10000, viscous=0, source=None, t=0.0, contents=None) -> Problem:
+    """source: dict(dir, sign, x, width, amp, freq, t0=0, ncyc=0) of the one-way acoustic source.
+    contents: None (polytropic gas) or dict(gam_b, Rg, Rv, T0, k_b, D_v, beta_T, beta_c) of the transfer
+    contents (the vapour pressure is the gas dict's pv)."""
     from workloads import WATER, AIR
     liquid = liquid or WATER
     gas = gas or AIR
@@ -130,7 +139,26 @@ def problem(ndim, n, dx, bc, nb, r0_median=10e-6, sigma_ln=0.3, cfl=0.3, liquid=
     pb.t = float(t)
     if source:
         set_source(pb, **source)
+    if contents:
+        set_contents(pb, **contents)
     return pb
+
+
+def set_contents(pb, gam_b, Rg, Rv, T0, k_b, D_v, beta_T, beta_c):
+    pb.contents = 1
+    pb.gam_b, pb.Rg, pb.Rv, pb.T0 = float(gam_b), float(Rg), float(Rv), float(T0)
+    pb.k_b, pb.D_v, pb.beta_T, pb.beta_c = float(k_b), float(D_v), float(beta_T), float(beta_c)
+
+
+def km_rddot_pb(pb, R, V, p_b, pdot_b, pinf, rho, c):
+    return lib().orc_km_rddot_pb(ctypes.byref(pb), R, V, p_b, pdot_b, pinf, rho, c)
+
+
+def contents_rates(pb, R, V, p_b, m_v, mg):
+    """(dp_b/dt, dm_v/dt) of one bubble with transfer contents."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    lib().orc_contents_rates(ctypes.byref(pb), R, V, p_b, m_v, mg, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
 
 
 def set_source(pb, dir, sign, x, width, amp, freq, t0=0.0, ncyc=0.0):
@@ -145,12 +173,13 @@ def source_amplitude(pb, t):
 
 
 def problem_from_case(case, **kw) -> Problem:
+    kw.setdefault("contents", getattr(case, "contents", None))
     return problem(case.ndim, case.n, case.dx, case.bc, case.nb, case.r0_median, case.sigma_ln,
                    case.cfl, case.liquid, case.gas, **kw)
 
 
 def nvar(pb) -> int:
-    return pb.ndim + 3 + 2 * pb.nb
+    return pb.ndim + 3 + (4 if pb.contents else 2) * pb.nb
 
 
 def ncells(pb) -> int:

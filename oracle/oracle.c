@@ -40,6 +40,16 @@
  *                   composition's observed order (2 at a trace void
  *                   fraction; 1 where the void fraction feeds back on p_l,
  *                   which the bin-by-bin sub-steps hold fixed).
+ *   transfer        Sec. 2 (gas and vapour contents with constant heat and
+ *   contents        mass transfer coefficients, eq. massVaporRate and the
+ *                   contents-pressure equation) -- pinned by equilibrium, the
+ *                   reduction to the polytropic model without transfer, the
+ *                   isothermal limit, the first law with vapour transfer, the
+ *                   hand-linearised heat-transfer oscillator at two radii,
+ *                   fixed-radius vapour relaxation, and the passive fluxes of
+ *                   n p_b and n m_v.  The coefficients are inputs (the paper
+ *                   does not give them); the sub-steps' error norm on p_b and
+ *                   m_v is parity unpinned.
  *   Lagrangian      Sec. 2.1 (kernel eq. kernel3D, smear, gather) -- pinned by
  *                   the kernel mass lattice sum, uniform gather, bubble at rest;
  *                   its liquid sources by exponential growth under a frozen
@@ -54,16 +64,18 @@
 
 #define ORC_PI 3.14159265358979323846
 #define NBMAX 64
-#define NWMAX (3 + 5 + 2 * NBMAX)
-#define NVMAX (3 + 3 + 2 * NBMAX)
+#define NWMAX (3 + 5 + 4 * NBMAX)
+#define NVMAX (3 + 3 + 4 * NBMAX)
 
 typedef struct {
     const orc_problem *pb;
     int nd, nb, nvar, nW;
+    int nf;                             /* fields per bin: 2 (R, Rdot) or 4 (and p_b, m_v) */
     int64_t N;
-    int iE, iA, iNR, iNV;               /* conserved slots */
-    int wPL, wA, wN, wB, wR, wV;        /* primitive slots */
+    int iE, iA, iNR, iNV, iNP, iNM;     /* conserved slots */
+    int wPL, wA, wN, wB, wR, wV, wP, wM; /* primitive slots */
     double r0[NBMAX], w[NBMAX], pg0[NBMAX];
+    double pb0[NBMAX], mv0[NBMAX], mg[NBMAX];  /* transfer contents at equilibrium; gas mass */
 } setup_t;
 
 typedef struct {
@@ -120,23 +132,45 @@ static int setup(const orc_problem *pb, setup_t *s)
         if (!(pb->src_width > 0.0) || !(pb->src_freq > 0.0) || !(pb->src_ncyc >= 0.0) || !isfinite(pb->src_amp))
             return -1;
     }
+    if (pb->contents < 0 || pb->contents > 1) return -1;
+    if (pb->contents == 1) {
+        if (!(pb->gam_b > 1.0) || !(pb->Rg > 0.0) || !(pb->Rv > 0.0) || !(pb->T0 > 0.0) || !(pb->k_b >= 0.0) ||
+            !(pb->D_v >= 0.0) || !(pb->beta_T >= 0.0) || !(pb->beta_c >= 0.0) || !(pb->pv >= 0.0) ||
+            !(pb->pv < pb->p0))
+            return -1;
+    }
     s->nd = pb->ndim;
     s->nb = pb->nb;
+    s->nf = pb->contents == 1 ? 4 : 2;
     if (orc_bins(pb->nb, pb->r0_median, pb->sigma_ln, s->r0, s->w) != 0) return -1;
-    for (int i = 0; i < s->nb; ++i) s->pg0[i] = pb->p0 + 2.0 * pb->sigma / s->r0[i] - pb->pv;
-    s->nvar = s->nd + 3 + 2 * s->nb;
-    s->nW = s->nd + 5 + 2 * s->nb;
+    for (int i = 0; i < s->nb; ++i) {
+        s->pg0[i] = pb->p0 + 2.0 * pb->sigma / s->r0[i] - pb->pv;
+        if (s->nf == 4) {
+            /* equilibrium: contents at the Laplace pressure, vapour at its saturation pressure p_v and the
+             * liquid temperature T0, the rest non-condensable gas at T0 */
+            double V0 = 4.0 * ORC_PI / 3.0 * s->r0[i] * s->r0[i] * s->r0[i];
+            s->pb0[i] = pb->p0 + 2.0 * pb->sigma / s->r0[i];
+            s->mv0[i] = pb->pv * V0 / (pb->Rv * pb->T0);
+            s->mg[i] = (s->pb0[i] - pb->pv) * V0 / (pb->Rg * pb->T0);
+        }
+    }
+    s->nvar = s->nd + 3 + s->nf * s->nb;
+    s->nW = s->nd + 5 + s->nf * s->nb;
     s->N = (int64_t)pb->n[0] * pb->n[1] * pb->n[2];
     s->iE = s->nd + 1;
     s->iA = s->nd + 2;
     s->iNR = s->nd + 3;
     s->iNV = s->nd + 3 + s->nb;
+    s->iNP = s->nd + 3 + 2 * s->nb;
+    s->iNM = s->nd + 3 + 3 * s->nb;
     s->wPL = s->nd + 1;
     s->wA = s->nd + 2;
     s->wN = s->nd + 3;
     s->wB = s->nd + 4;
     s->wR = s->nd + 5;
     s->wV = s->nd + 5 + s->nb;
+    s->wP = s->nd + 5 + 2 * s->nb;
+    s->wM = s->nd + 5 + 3 * s->nb;
     return 0;
 }
 
@@ -252,6 +286,46 @@ double orc_km_rddot(const orc_problem *pb, double R, double V, double R0, double
     return num / den;
 }
 
+/* Keller--Miksis with the contents' pressure p_b and its rate given (transfer contents). */
+double orc_km_rddot_pb(const orc_problem *pb, double R, double V, double p_b, double pdot_b,
+                       double pinf, double rho, double c)
+{
+    double pbw = p_b - 4.0 * pb->mu * V / R - 2.0 * pb->sigma / R;
+    double dpbw = pdot_b + 4.0 * pb->mu * V * V / (R * R) + 2.0 * pb->sigma * V / (R * R);
+    double num = (1.0 + V / c) * (pbw - pinf) / rho + R * dpbw / (rho * c)
+                 - 1.5 * V * V * (1.0 - V / (3.0 * c));
+    double den = R * (1.0 - V / c) + 4.0 * pb->mu / (rho * c);
+    return num / den;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Transfer contents (Sec. 2: constant heat and mass transfer coefficients at */
+/* the wall, eq. massVaporRate, and the contents-pressure equation).        */
+/* The contents are an ideal-gas mixture of gas (fixed mass mg) and vapour  */
+/* (mass m) at uniform pressure p; its mean temperature follows from        */
+/* p V = (mg Rg + m Rv) Tbar.  The wall stays at the liquid temperature T0  */
+/* with the vapour at its saturation pressure p_v there, which fixes the    */
+/* wall's vapour mass fraction chi_w and mixture density rho_w.  The wall   */
+/* gradients of T and of the vapour mass fraction are the transfer          */
+/* coefficients times (wall value - bubble mean) / R.                       */
+/* ------------------------------------------------------------------------ */
+void orc_contents_rates(const orc_problem *pb, double R, double V, double p, double m, double mg,
+                        double *pdot, double *mdot)
+{
+    double vol = 4.0 * ORC_PI / 3.0 * R * R * R;
+    double Tbar = p * vol / (mg * pb->Rg + m * pb->Rv);
+    double chibar = m / (m + mg);
+    double chiw = pb->pv * pb->Rg / (pb->pv * pb->Rg + (p - pb->pv) * pb->Rv);
+    double Rw = chiw * pb->Rv + (1.0 - chiw) * pb->Rg;
+    double rhow = p / (Rw * pb->T0);
+    double dTdr = pb->beta_T * (pb->T0 - Tbar) / R;
+    double dchidr = pb->beta_c * (chiw - chibar) / R;
+    double flux = pb->D_v * rhow / (1.0 - chiw) * dchidr;   /* vapour mass into the bubble per wall area */
+    *pdot = 3.0 * pb->gam_b / R
+            * (-V * p + pb->Rv * pb->T0 * flux + (pb->gam_b - 1.0) / pb->gam_b * pb->k_b * dTdr);
+    *mdot = 4.0 * ORC_PI * R * R * flux;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Conserved -> primitive, bin moments and mixture pressure (Sec. 2, 2.2).  */
 /* ------------------------------------------------------------------------ */
@@ -282,7 +356,14 @@ static void primitives(const setup_t *s, const double *qc, double *W, aux_t *ax)
             double V = qc[s->iNV + i] / n;
             W[s->wR + i] = R;
             W[s->wV + i] = V;
-            double pbub = s->pg0[i] * pow(s->r0[i] / R, 3.0 * pb->kappa);
+            double pbub;
+            if (s->nf == 4) {
+                pbub = qc[s->iNP + i] / n;
+                W[s->wP + i] = pbub;
+                W[s->wM + i] = qc[s->iNM + i] / n;
+            } else {
+                pbub = s->pg0[i] * pow(s->r0[i] / R, 3.0 * pb->kappa);
+            }
             double pbw = pbub - 4.0 * pb->mu * V / R - 2.0 * pb->sigma / R;
             double R3 = R * R * R;
             M3 += s->w[i] * R3;
@@ -295,6 +376,10 @@ static void primitives(const setup_t *s, const double *qc, double *W, aux_t *ax)
         for (int i = 0; i < s->nb; ++i) {
             W[s->wR + i] = s->r0[i];
             W[s->wV + i] = 0.0;
+            if (s->nf == 4) {
+                W[s->wP + i] = s->pb0[i];
+                W[s->wM + i] = s->mv0[i];
+            }
             M3 += s->w[i] * pow(s->r0[i], 3.0);
         }
     }
@@ -388,6 +473,10 @@ int orc_hllc(const orc_problem *pb, int dir, const double *WL, const double *WR,
     for (int i = 0; i < s.nb; ++i) {
         F[s.iNR + i] = K->n * WK[s.wR + i] * un;
         F[s.iNV + i] = K->n * WK[s.wV + i] * un;
+        if (s.nf == 4) {
+            F[s.iNP + i] = K->n * WK[s.wP + i] * un;
+            F[s.iNM + i] = K->n * WK[s.wM + i] * un;
+        }
     }
     if (star) {
         double fac = SK * (Ss - un) / (SK - Ss);
@@ -398,6 +487,10 @@ int orc_hllc(const orc_problem *pb, int dir, const double *WL, const double *WR,
         for (int i = 0; i < s.nb; ++i) {
             F[s.iNR + i] += fac * K->n * WK[s.wR + i];
             F[s.iNV + i] += fac * K->n * WK[s.wV + i];
+            if (s.nf == 4) {
+                F[s.iNP + i] += fac * K->n * WK[s.wP + i];
+                F[s.iNM + i] += fac * K->n * WK[s.wM + i];
+            }
         }
     }
     return 0;
@@ -444,6 +537,10 @@ static void face_flux(const setup_t *s, int dir, double (*Wst)[NWMAX], double *F
             if (!(WK[s->wR + i] > 0.0)) {
                 WK[s->wR + i] = Wc[s->wR + i];
                 WK[s->wV + i] = Wc[s->wV + i];
+                if (s->nf == 4) {
+                    WK[s->wP + i] = Wc[s->wP + i];
+                    WK[s->wM + i] = Wc[s->wM + i];
+                }
             }
         }
     }
@@ -526,7 +623,15 @@ static void cell_sources(const setup_t *s, const double *W, const aux_t *ax, dou
     for (int i = 0; i < s->nb; ++i) {
         double R = W[s->wR + i], V = W[s->wV + i];
         L[s->iNR + i] += n * V;
-        L[s->iNV + i] += n * orc_km_rddot(pb, R, V, s->r0[i], s->pg0[i], W[s->wPL], ax->rhol, ax->c);
+        if (s->nf == 4) {
+            double pdot, mdot;
+            orc_contents_rates(pb, R, V, W[s->wP + i], W[s->wM + i], s->mg[i], &pdot, &mdot);
+            L[s->iNV + i] += n * orc_km_rddot_pb(pb, R, V, W[s->wP + i], pdot, W[s->wPL], ax->rhol, ax->c);
+            L[s->iNP + i] += n * pdot;
+            L[s->iNM + i] += n * mdot;
+        } else {
+            L[s->iNV + i] += n * orc_km_rddot(pb, R, V, s->r0[i], s->pg0[i], W[s->wPL], ax->rhol, ax->c);
+        }
     }
 }
 
@@ -693,6 +798,10 @@ int orc_init_state(const orc_problem *pb, const double *prim, double *q)
         for (int i = 0; i < s.nb; ++i) {
             q[(int64_t)(s.iNR + i) * N + c] = n * s.r0[i];
             q[(int64_t)(s.iNV + i) * N + c] = 0.0;
+            if (s.nf == 4) {
+                q[(int64_t)(s.iNP + i) * N + c] = n * s.pb0[i];
+                q[(int64_t)(s.iNM + i) * N + c] = n * s.mv0[i];
+            }
         }
     }
     return 0;
@@ -812,6 +921,58 @@ static int bubble_ode(const orc_problem *pb, double R0, double pg0, double pl, d
     return accepted;
 }
 
+/* The same embedded pair and step control for the transfer contents' (R, Rdot, p_b, m_v); the error
+ * norm adds |dp|/|p| and |dm|/(|m| + mg) (vapour mass against the bubble's whole contents). */
+static void tr_rates(const orc_problem *pb, double mg, double pl, double rhol, double c, const double *y,
+                     double *f)
+{
+    double pdot, mdot;
+    orc_contents_rates(pb, y[0], y[1], y[2], y[3], mg, &pdot, &mdot);
+    f[0] = y[1];
+    f[1] = orc_km_rddot_pb(pb, y[0], y[1], y[2], pdot, pl, rhol, c);
+    f[2] = pdot;
+    f[3] = mdot;
+}
+
+static int bubble_ode_tr(const orc_problem *pb, double mg, double pl, double rhol, double c, double tau,
+                         double *y)
+{
+    const double rtol = pb->sub_rtol;
+    const double vfloor = 1e-3 * sqrt(pb->p0 / pb->rho0);
+    double t = 0.0, h = tau;
+    int accepted = 0, attempts = 0;
+    while (t < tau) {
+        if (attempts >= pb->max_substeps) return -1;
+        ++attempts;
+        if (h > tau - t) h = tau - t;
+        double k1[4], k2[4], k3[4], a[4], b[4], e[4], nn[4];
+        tr_rates(pb, mg, pl, rhol, c, y, k1);
+        for (int j = 0; j < 4; ++j) a[j] = y[j] + h * k1[j];
+        tr_rates(pb, mg, pl, rhol, c, a, k2);
+        for (int j = 0; j < 4; ++j) {
+            b[j] = 0.75 * y[j] + 0.25 * (a[j] + h * k2[j]);
+            e[j] = y[j] + 0.5 * h * (k1[j] + k2[j]);
+        }
+        tr_rates(pb, mg, pl, rhol, c, b, k3);
+        for (int j = 0; j < 4; ++j) nn[j] = y[j] / 3.0 + 2.0 / 3.0 * (b[j] + h * k3[j]);
+        double err = fmax(fabs(nn[0] - e[0]) / fabs(nn[0]), fabs(nn[1] - e[1]) / fmax(fabs(nn[1]), vfloor));
+        err = fmax(err, fabs(nn[2] - e[2]) / fabs(nn[2]));
+        err = fmax(err, fabs(nn[3] - e[3]) / (fabs(nn[3]) + mg));
+        if (!(err == err)) err = INFINITY;
+        if (err <= rtol && nn[0] > 0.0 && nn[2] > 0.0) {
+            t += h;
+            for (int j = 0; j < 4; ++j) y[j] = nn[j];
+            ++accepted;
+        }
+        double fac = err > 0.0 ? 0.9 * pow(rtol / err, 1.0 / 3.0) : 4.0;
+        if (!(nn[0] > 0.0) || !(nn[2] > 0.0)) fac = 0.25;
+        if (fac > 4.0) fac = 4.0;
+        if (fac < 0.25) fac = 0.25;
+        h *= fac;
+    }
+    return accepted;
+}
+
 int orc_bubble_advance(const orc_problem *pb, double *q, double dt, int32_t *nsub_out)
 {
     setup_t s;
@@ -834,7 +995,17 @@ int orc_bubble_advance(const orc_problem *pb, double *q, double dt, int32_t *nsu
         double m3new = 0.0;
         for (int i = 0; i < s.nb; ++i) {
             double R = W[s.wR + i], V = W[s.wV + i];
-            int ns = bubble_ode(pb, s.r0[i], s.pg0[i], W[s.wPL], ax.rhol, ax.c, dt, &R, &V);
+            int ns;
+            if (s.nf == 4) {
+                double y[4] = {R, V, W[s.wP + i], W[s.wM + i]};
+                ns = bubble_ode_tr(pb, s.mg[i], W[s.wPL], ax.rhol, ax.c, dt, y);
+                R = y[0];
+                V = y[1];
+                q[(int64_t)(s.iNP + i) * N + c] = n * y[2];
+                q[(int64_t)(s.iNM + i) * N + c] = n * y[3];
+            } else {
+                ns = bubble_ode(pb, s.r0[i], s.pg0[i], W[s.wPL], ax.rhol, ax.c, dt, &R, &V);
+            }
             if (ns < 0) fail = 1;
             if (nsub_out) nsub_out[(int64_t)i * N + c] = ns;
             q[(int64_t)(s.iNR + i) * N + c] = n * R;

@@ -15,6 +15,9 @@
  *   rho, rho*u_1..ndim, E, alpha, (n R)_1..nb, (n Rdot)_1..nb
  * (mixture conservation laws, Sec. 2 eq. euler_transport; void fraction
  * and bin transport, Sec. 2.2 eqs. e:alpha and the bin-variable equation).
+ * With transfer contents (contents = 1) nvar = ndim + 3 + 4 nb: the slots
+ * above, then (n p_b)_1..nb and (n m_v)_1..nb (Sec. 2.2 lists p_b and m_v
+ * among the bin variables).
  *
  * Parity status per function is given in the header comment of oracle.c.
  */
@@ -52,6 +55,18 @@ typedef struct {
     double src_freq;     /* frequency (Hz) */
     double src_t0;       /* start time of the sine */
     double src_ncyc;     /* cycles emitted (0: continuous) */
+    /* Bubble contents (Sec. 2).  0: polytropic gas, p_b = p_g0 (R0/R)^(3 kappa).  1: gas and vapour
+     * with heat and vapour transfer at the wall through constant transfer coefficients (the reduced
+     * model the paper adopts: eq. massVaporRate and the contents-pressure equation after it); the
+     * state then carries (n p_b)_i and (n m_v)_i per bin as well. */
+    int contents;
+    double gam_b;        /* specific-heat ratio of the contents */
+    double Rg, Rv;       /* gas constants of the non-condensable gas and of the vapour (J/(kg K)) */
+    double T0;           /* liquid temperature, which the bubble wall keeps (K) */
+    double k_b;          /* thermal conductivity of the contents (W/(m K)) */
+    double D_v;          /* binary diffusion coefficient of vapour in the gas (m^2/s) */
+    double beta_T;       /* heat transfer coefficient: dT/dr at the wall = beta_T (T0 - Tbar) / R */
+    double beta_c;       /* mass transfer coefficient: dchi/dr at the wall = beta_c (chi_w - chibar) / R */
 } orc_problem;
 
 /* Bins: ln(R0/R_med) on [-3 sigma, 3 sigma], composite Simpson weights of the
@@ -100,6 +115,18 @@ void orc_set_threads(int n);
 /* Keller--Miksis wall acceleration with polytropic contents (Sec. 2 eq. keller_miksis). */
 double orc_km_rddot(const orc_problem *pb, double R, double Rdot, double R0, double pg0,
                     double p_inf, double rho, double c);
+
+/* Keller--Miksis wall acceleration for contents of pressure p_b changing at the rate pdot_b
+ * (Sec. 2 eq. keller_miksis with p_bw from p_b). */
+double orc_km_rddot_pb(const orc_problem *pb, double R, double Rdot, double p_b, double pdot_b,
+                       double p_inf, double rho, double c);
+
+/* Transfer contents of one bubble (gas mass mg, radius R, wall velocity Rdot, pressure p_b, vapour
+ * mass m_v): the rates dp_b/dt and dm_v/dt (Sec. 2, eq. massVaporRate and the contents-pressure
+ * equation).  The bin's equilibrium: p_b = p0 + 2 sigma/R0, m_v = p_v V0/(R_v T0),
+ * mg = (p_b - p_v) V0/(R_g T0) with V0 = 4/3 pi R0^3. */
+void orc_contents_rates(const orc_problem *pb, double R, double Rdot, double p_b, double m_v, double mg,
+                        double *pdot_b, double *mdot_v);
 
 /* WENO5-JS value at the right face of the centre cell from v[0..4] = cells i-2..i+2. */
 double orc_weno5(const double *v);

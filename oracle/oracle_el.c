@@ -36,6 +36,7 @@ double orc_el_kernel(double d, double h)
 static int el_check(const orc_problem *pb)
 {
     if (pb->ndim != 3) return -7;
+    if (pb->contents != 0) return -1;   /* the Lagrangian bubbles carry polytropic contents only */
     for (int d = 0; d < 3; ++d) {
         if (pb->n[d] < 3 || !(pb->dx[d] > 0.0)) return -1;
         if (pb->dx[d] != pb->dx[0]) return -1;

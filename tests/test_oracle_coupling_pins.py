@@ -24,6 +24,7 @@ import numpy as np
 import pytest
 
 from tests import exact_riemann
+import workloads as W
 
 
 # ---------------------------------------------------------------------------
@@ -78,37 +79,44 @@ def test_hllc_passive_fluxes_carry_upwind_specific_values(orc):
     """HLLC moves a passive specific quantity phi/rho with the mass flux from the upwind side of the
     contact: F_phi = (phi/rho)_K F_rho, K = L where F_rho > 0 (the star density is positive, so the
     mass flux has the sign of the contact speed) and R where F_rho < 0.  This holds in every branch
-    (supersonic and both star states) for alpha, n R_i and n Rdot_i, whatever the pressures."""
+    (supersonic and both star states) for alpha, n R_i and n Rdot_i (and n p_b,i, n m_v,i of transfer
+    contents), whatever the pressures."""
     rng = np.random.default_rng(21)
     nb, hit = 3, {0: 0, 1: 0}
-    for ndim in (1, 2, 3):
-        pb = orc.problem(ndim, (8, 8 if ndim > 1 else 1, 8 if ndim > 2 else 1), (1e-4,) * 3, ((0, 0),) * 3, nb)
-        nd = ndim
-        for _ in range(300):
-            sides = []
-            for _s in range(2):
-                rho = 1000 * rng.uniform(0.9, 1.1)
-                u = rng.normal(size=nd) * rng.choice([5.0, 300.0, 2500.0])
-                pl = 1e5 * rng.uniform(0.2, 20.0)
-                a = rng.uniform(1e-5, 1e-2)
-                n = 1e10 * rng.uniform(0.5, 2)
-                B = 1e5 * rng.uniform(0.5, 2)
-                R = 1e-5 * rng.uniform(0.5, 2, size=nb)
-                V = rng.normal(size=nb) * 3
-                sides.append(np.concatenate([[rho], u, [pl, a, n, B], R, V]))
-            WL, WR = sides
-            for d in range(nd):
-                F = orc.hllc(pb, d, WL, WR)
-                if F[0] == 0.0:
-                    continue
-                K = WL if F[0] > 0 else WR
-                hit[int(F[0] > 0)] += 1
-                rho, a, n = K[0], K[nd + 2], K[nd + 3]
-                R, V = K[nd + 5:nd + 5 + nb], K[nd + 5 + nb:]
-                spec = np.concatenate([[a], n * R, n * V]) / rho
-                got = F[nd + 2:]
-                assert np.allclose(got, spec * F[0], rtol=1e-11, atol=0), (ndim, d)
-    assert min(hit.values()) > 100
+    for contents in (None, W.AIR_VAPOUR):
+        nf = 4 if contents else 2
+        for ndim in (1, 2, 3):
+            pb = orc.problem(ndim, (8, 8 if ndim > 1 else 1, 8 if ndim > 2 else 1), (1e-4,) * 3, ((0, 0),) * 3, nb,
+                             contents=contents)
+            nd = ndim
+            for _ in range(300):
+                sides = []
+                for _s in range(2):
+                    rho = 1000 * rng.uniform(0.9, 1.1)
+                    u = rng.normal(size=nd) * rng.choice([5.0, 300.0, 2500.0])
+                    pl = 1e5 * rng.uniform(0.2, 20.0)
+                    a = rng.uniform(1e-5, 1e-2)
+                    n = 1e10 * rng.uniform(0.5, 2)
+                    B = 1e5 * rng.uniform(0.5, 2)
+                    R = 1e-5 * rng.uniform(0.5, 2, size=nb)
+                    V = rng.normal(size=nb) * 3
+                    P = 1e5 * rng.uniform(0.5, 3, size=nb)
+                    M = 1e-16 * rng.uniform(0.5, 2, size=nb)
+                    sides.append(np.concatenate([[rho], u, [pl, a, n, B], R, V] + ([P, M] if contents else [])))
+                WL, WR = sides
+                for d in range(nd):
+                    F = orc.hllc(pb, d, WL, WR)
+                    if F[0] == 0.0:
+                        continue
+                    K = WL if F[0] > 0 else WR
+                    hit[int(F[0] > 0)] += 1
+                    rho, a, n = K[0], K[nd + 2], K[nd + 3]
+                    bins_K = K[nd + 5:nd + 5 + nf * nb]
+                    spec = np.concatenate([[a], n * bins_K]) / rho
+                    got = F[nd + 2:]
+                    assert got.shape == spec.shape
+                    assert np.allclose(got, spec * F[0], rtol=1e-11, atol=0), (ndim, d, contents)
+    assert min(hit.values()) > 200
 
 
 # ---------------------------------------------------------------------------

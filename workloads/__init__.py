@@ -52,6 +52,14 @@ ATM = 101325.0
 WATER = dict(gamma=7.1, pi_inf=3.06e8, rho0=1000.0, p0=101325.0)
 AIR = dict(kappa=1.4, sigma=0.0728, mu=1.0e-3, pv=0.0)
 
+# Bubble contents with heat and vapour transfer: air and water vapour at 20 C (handbook properties; the
+# paper gives none).  The transfer coefficients beta = 5 are those of a parabolic profile inside the bubble
+# (f - f_wall proportional to 1 - r^2/R^2 has wall gradient 5 (f_wall - mean)/R), the slow-oscillation
+# limit; callers pass their own.  The vapour pressure is the gas dict's pv.
+AIR_VAPOUR = dict(gam_b=1.4, Rg=287.06, Rv=461.52, T0=293.15, k_b=0.0257, D_v=2.42e-5, beta_T=5.0, beta_c=5.0)
+PV_WATER_20C = 2339.0
+AIR_WITH_VAPOUR = dict(AIR, pv=PV_WATER_20C)
+
 # Boundary codes shared by both sides' problem descriptions.
 BC_PERIODIC = 0
 BC_REFLECTIVE = 1
@@ -80,6 +88,7 @@ class Case:
     prim: np.ndarray    # [ndim+3][N]: rho_l, u_1..ndim, p_l, alpha
     liquid: dict = field(default_factory=lambda: dict(WATER))
     gas: dict = field(default_factory=lambda: dict(AIR))
+    contents: dict | None = None   # None: polytropic gas; else transfer-contents constants (AIR_VAPOUR)
 
     @property
     def ncells(self) -> int:
@@ -87,7 +96,7 @@ class Case:
 
     @property
     def nvar(self) -> int:
-        return self.ndim + 3 + 2 * self.nb
+        return self.ndim + 3 + (4 if self.contents else 2) * self.nb
 
 
 def _centres(n: int, dx: float) -> np.ndarray:
