@@ -94,7 +94,8 @@ def cpu_baseline(case) -> dict:
     t0 = time.perf_counter()
     oracle.rk3_step(pb, q, dt)
     t = time.perf_counter() - t0
-    small = workloads.c2(n=256, nb=case.nb)
+    import dataclasses
+    small = dataclasses.replace(workloads.c2(n=256, nb=case.nb), gas=case.gas, contents=case.contents)
     pbs = oracle.problem_from_case(small)
     qs = oracle.init_state(pbs, small.prim)
     dts = oracle.cfl_dt(pbs, qs)
@@ -271,6 +272,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     ap.add_argument("--workload", choices=["stage", "serving", "collapse3d", "lagrangian"], default="stage")
+    ap.add_argument("--contents", choices=["polytropic", "transfer"], default="polytropic",
+                    help="stage: bubble contents (transfer: gas and vapour with heat and vapour transfer)")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--rate", type=float, default=20.0, help="serving: mean arrivals per second")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: HBM budget for resident solves")
@@ -314,6 +317,9 @@ def main():
     import workloads
     import paper_2511_21031_amd as bub
     case = workloads.c2()
+    if args.contents == "transfer":
+        import dataclasses
+        case = dataclasses.replace(case, gas=dict(workloads.AIR_WITH_VAPOUR), contents=dict(workloads.AIR_VAPOUR))
     N, nb = case.ncells, case.nb
     first = args.precision
     runs = {first: stage_run(bub, torch, case, first, args)}
@@ -344,7 +350,9 @@ def main():
         "dtype": "f64" if first == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": "2D 1024x1024 periodic ensemble-averaged, 31 log-normal bins (sigma 0.5), "
-                               "1 atm plane sine wave, CFL 0.3",
+                               "1 atm plane sine wave, CFL 0.3"
+                               + (", gas and vapour contents with heat and vapour transfer (air/water vapour, "
+                                  "20 C, transfer coefficients 5)" if args.contents == "transfer" else ""),
                    "cells": N, "bins": nb, "nvar": nvar, "precision": first,
                    "tile": r["tile"], "autotune_ms": r["autotune_ms"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -407,7 +415,8 @@ def stage_run(bub, torch, case, precision, args) -> dict:
            "k_prim_avg_ms": prim_ms / max(prim_n, 1), "k_prim_launches": prim_n,
            "other_avg_ms": other_ms / max(other_n, 1), "other_launches": other_n,
            "tile": [tx, ty, tz, blk], "autotune_ms": [round(m, 4) for m in tile_ms], "nvar": ctx.nvar,
-           "kname": f"void bub::k_stage<2, {tx}, {ty}, {tz}, {blk}, {tf}, true, true>"}
+           "kname": (f"void bub::k_stage<2, {tx}, {ty}, {tz}, {blk}, {tf}, true, 1>" if case.contents is None
+                     else f"void bub::k_stage<2, {tx}, {ty}, {tz}, {blk}, {tf}, false, 2>")}
     print(f"[stage] {precision}: {res['ms_per_step']:.3f} ms per step, stage kernel {res['k_stage_avg_ms']:.3f} ms, "
           f"primitive pass {res['k_prim_avg_ms']:.3f} ms x {prim_n}", file=sys.stderr, flush=True)
     del q, work, ctx

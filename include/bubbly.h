@@ -80,6 +80,25 @@ typedef struct { double kappa, sigma, mu, pv; } bub_gas;
  * [-3 sigma_ln, 3 sigma_ln], composite Simpson weights of the normal pdf, normalised. */
 typedef struct { int nb; double r0_median, sigma_ln; } bub_bins;
 
+/* Bubble contents (Sec. 2).  BUB_CONTENTS_POLYTROPIC: gas with p_b = p_g0 (R0/R)^(3 kappa),
+ * p_g0 = p0 + 2 sigma/R0 - pv.  BUB_CONTENTS_TRANSFER: gas and vapour with heat and vapour transfer
+ * at the wall through constant transfer coefficients (eq. massVaporRate and the contents-pressure
+ * equation that follows it).  The state then carries, after (n Rdot)_i, (n p_b)_i and (n m_v)_i per
+ * bin (nvar = ndim + 3 + 4 nb; p_b the contents' pressure, m_v the vapour mass of one bubble),
+ * gas.kappa is not used and gas.pv is the vapour's saturation pressure at T0 (0 <= pv < p0).  Per
+ * bubble: Tbar = p_b V/(m_g Rg + m_v Rv) with the bin's gas mass m_g = (p_b0 - pv) V0/(Rg T0);
+ * the wall stays at T0 with its vapour saturated; wall gradients dT/dr = beta_T (T0 - Tbar)/R and
+ * dchi/dr = beta_c (chi_w - m_v/(m_v + m_g))/R; dm_v/dt = 4 pi R^2 D_v rho_w/(1 - chi_w) dchi/dr;
+ * dp_b/dt = 3 gam_b/R (-Rdot p_b + Rv T0 dm_v/dt/(4 pi R^2) + (gam_b - 1)/gam_b k_b dT/dr).  At
+ * equilibrium p_b0 = p0 + 2 sigma/R0 and m_v0 = pv V0/(Rv T0).  The paper does not give the
+ * coefficients: the caller does.  Ensemble-averaged model only (the Lagrangian calls return
+ * BUB_EUNSUPPORTED); stage shape 0 with the separate primitive pass.  gam_b: specific-heat ratio of
+ * the contents; Rg, Rv: gas constants of gas and vapour (J/(kg K)); T0: liquid temperature (K);
+ * k_b: thermal conductivity of the contents (W/(m K)); D_v: vapour-gas diffusion coefficient
+ * (m^2/s); beta_T, beta_c: the transfer coefficients (>= 0). */
+enum { BUB_CONTENTS_POLYTROPIC = 0, BUB_CONTENTS_TRANSFER = 1 };
+typedef struct { double gam_b, Rg, Rv, T0, k_b, D_v, beta_T, beta_c; } bub_transfer;
+
 /* Options.  cfl: time step fraction for dt <= 0 requests.  precision:
  * BUB_PREC_FP64 or BUB_PREC_MIXED (FP32 reconstruction/Riemann/flux differences,
  * FP64 primitives, moments, Keller--Miksis, sources and RK accumulation).
@@ -95,8 +114,18 @@ typedef struct { int nb; double r0_median, sigma_ln; } bub_bins;
  * The stress is added by a pass after each stage kernel (so the stages of a
  * viscous problem take a separate primitive pass).  The time step stays the
  * acoustic CFL step (the viscous limit dx^2/(2 ndim nu) is far larger at
- * bubbly-flow scales). */
-typedef struct { double cfl; int precision; int bubble_mode; double sub_rtol; int max_substeps; int viscous; } bub_opts;
+ * bubbly-flow scales).  contents: BUB_CONTENTS_POLYTROPIC or BUB_CONTENTS_TRANSFER
+ * (below); transfer: its constants (ignored for polytropic contents). */
+typedef struct {
+    double cfl;
+    int precision;
+    int bubble_mode;
+    double sub_rtol;
+    int max_substeps;
+    int viscous;
+    int contents;
+    bub_transfer transfer;
+} bub_opts;
 
 typedef struct bub_ctx bub_ctx;
 
@@ -167,7 +196,7 @@ int bub_rk3_step(bub_ctx *ctx, double *q, double *work, double dt, double *dt_de
  * result is bitwise that of bub_rhs_stage on a context of the same problem.  err
  * (device int64[3], may be NULL) receives the device error word (code, first
  * failing cell or -1, failing bin or -1) after the call's kernels.
- * BUB_ENOMEM if the problem's buffers, 9984 + 8*(ndim+6)*N bytes, exceed the
+ * BUB_ENOMEM if the problem's buffers, 11520 + 8*(ndim+6)*N bytes, exceed the
  * static array (2D grids up to 723^2 cells fit, 3D up to 77^3); the argument
  * errors of bub_ctx_create and
  * bub_rhs_stage.  Every call on one GPU uses that GPU's array: calls whose work

@@ -11,9 +11,9 @@ fallback).
 from __future__ import annotations
 
 from ._binding import (BubblyError, Batch, Context, lib, library_path, BC_PERIODIC, BC_REFLECTIVE,
-                       PREC_FP64, PREC_MIXED, BUBBLES_UNSPLIT, BUBBLES_SPLIT, context_from_case,
-                       ctx_buffer_bytes)
+                       PREC_FP64, PREC_MIXED, BUBBLES_UNSPLIT, BUBBLES_SPLIT, CONTENTS_POLYTROPIC,
+                       CONTENTS_TRANSFER, context_from_case, ctx_buffer_bytes)
 
 __all__ = ["BubblyError", "Batch", "Context", "lib", "library_path", "context_from_case", "BC_PERIODIC",
            "BC_REFLECTIVE", "PREC_FP64", "PREC_MIXED", "BUBBLES_UNSPLIT", "BUBBLES_SPLIT",
-           "ctx_buffer_bytes"]
+           "CONTENTS_POLYTROPIC", "CONTENTS_TRANSFER", "ctx_buffer_bytes"]

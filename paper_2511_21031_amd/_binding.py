@@ -12,6 +12,7 @@ _SO = os.path.join(_HERE, "libbubbly.so")
 BC_PERIODIC, BC_REFLECTIVE = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 BUBBLES_UNSPLIT, BUBBLES_SPLIT = 0, 1
+CONTENTS_POLYTROPIC, CONTENTS_TRANSFER = 0, 1
 
 
 class BubblyError(RuntimeError):
@@ -40,9 +41,14 @@ class _Bins(ctypes.Structure):
     _fields_ = [("nb", ctypes.c_int), ("r0_median", ctypes.c_double), ("sigma_ln", ctypes.c_double)]
 
 
+class _Transfer(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("gam_b", "Rg", "Rv", "T0", "k_b", "D_v", "beta_T", "beta_c")]
+
+
 class _Opts(ctypes.Structure):
     _fields_ = [("cfl", ctypes.c_double), ("precision", ctypes.c_int), ("bubble_mode", ctypes.c_int),
-                ("sub_rtol", ctypes.c_double), ("max_substeps", ctypes.c_int), ("viscous", ctypes.c_int)]
+                ("sub_rtol", ctypes.c_double), ("max_substeps", ctypes.c_int), ("viscous", ctypes.c_int),
+                ("contents", ctypes.c_int), ("transfer", _Transfer)]
 
 
 class _Source(ctypes.Structure):
@@ -161,9 +167,11 @@ class Context:
 
     def __init__(self, ndim, n, dx, bc, nb, r0_median=10e-6, sigma_ln=0.3, liquid=None, gas=None, cfl=0.3,
                  precision=PREC_FP64, bubble_mode=BUBBLES_UNSPLIT, sub_rtol=1e-4, max_substeps=10000,
-                 torch_buffer=False, stream=None, viscous=0, source=None):
+                 torch_buffer=False, stream=None, viscous=0, source=None, contents=None):
         """torch_buffer=True: the context's device memory is a torch tensor and it is initialised on
-        `stream` (bub_ctx_create_on): no allocation call and no host synchronisation."""
+        `stream` (bub_ctx_create_on): no allocation call and no host synchronisation.  contents: None for
+        polytropic gas, or dict(gam_b, Rg, Rv, T0, k_b, D_v, beta_T, beta_c) for gas and vapour with heat
+        and vapour transfer (the vapour pressure is gas['pv'])."""
         L = lib()
         liquid = liquid or dict(gamma=7.1, pi_inf=3.06e8, rho0=1000.0, p0=101325.0)
         gas = gas or dict(kappa=1.4, sigma=0.0728, mu=1e-3, pv=0.0)
@@ -178,6 +186,9 @@ class Context:
         gs = _Gas(gas["kappa"], gas["sigma"], gas["mu"], gas["pv"])
         bn = _Bins(nb, r0_median, sigma_ln)
         op = _Opts(cfl, precision, bubble_mode, sub_rtol, max_substeps, int(viscous))
+        if contents:
+            op.contents = CONTENTS_TRANSFER
+            op.transfer = _Transfer(*(float(contents[k]) for k, _ in _Transfer._fields_))
         h = _vp()
         self._buf = None
         if torch_buffer:
@@ -522,6 +533,7 @@ class Batch:
 
 
 def context_from_case(case, **kw) -> Context:
-    """Context for a ``workloads.Case`` (grid, bins, physics and CFL of the case)."""
+    """Context for a ``workloads.Case`` (grid, bins, physics, contents and CFL of the case)."""
+    kw.setdefault("contents", getattr(case, "contents", None))
     return Context(case.ndim, case.n, case.dx, case.bc, case.nb, case.r0_median, case.sigma_ln, case.liquid,
                    case.gas, case.cfl, **kw)

@@ -123,31 +123,40 @@ void tile_info(int *tx, int *ty, int *tz, int *block)
     *block = Tile<D, V>::BLOCK;
 }
 
-// The kernels take the polytropic power x^(3 kappa) in one of two compiled forms: the fifth-root
-// Newton form when 3 kappa is a whole number of fifths (air's 4.2, 3, 5, ...), the general
-// exp2(3 kappa log2 x) form otherwise.  The general form has only stage shape 0 and no fused epilogue.
-bool pw_fast(const bub_ctx *c) { return c->ph.pw_c > 0; }
+// The kernels are compiled for the bubble contents (Contents): polytropic gas whose power x^(3 kappa)
+// takes the fifth-root Newton form when 3 kappa is a whole number of fifths (air's 4.2, 3, 5, ...) or the
+// general exp2(3 kappa log2 x) form otherwise, or transfer contents.  Only the fifth-root form has every
+// stage shape and the fused epilogue; the others run stage shape 0 with the separate primitive pass.
+int ct_of(const bub_ctx *c)
+{
+    if (c->opts.contents == BUB_CONTENTS_TRANSFER) return CT_TRANSFER;
+    return c->ph.pw_c > 0 ? CT_FIFTHS : CT_POLY;
+}
+bool pw_fast(const bub_ctx *c) { return ct_of(c) == CT_FIFTHS; }
 
-template <int D, int S, int CELLS, bool PW>
+template <int D, int S, int CELLS, int CT>
 void launch_prim_p(bub_ctx *c, const double *q, double *out, int mode, hipStream_t s)
 {
     const dim3 grid((unsigned)((c->g.N + CELLS - 1) / CELLS)), block(S * CELLS);
     if (mode == PRIM_CFL)
-        hipLaunchKernelGGL((k_prim<D, PRIM_CFL, S, CELLS, PW>), grid, block, 0, s, q, out, c->g, c->ph, c->bt,
+        hipLaunchKernelGGL((k_prim<D, PRIM_CFL, S, CELLS, CT>), grid, block, 0, s, q, out, c->g, c->ph, c->bt,
                            c->d_sc);
     else if (mode == PRIM_MOMENTS)
-        hipLaunchKernelGGL((k_prim<D, PRIM_MOMENTS, S, CELLS, PW>), grid, block, 0, s, q, out, c->g, c->ph, c->bt,
+        hipLaunchKernelGGL((k_prim<D, PRIM_MOMENTS, S, CELLS, CT>), grid, block, 0, s, q, out, c->g, c->ph, c->bt,
                            c->d_sc);
     else
-        hipLaunchKernelGGL((k_prim<D, PRIM_ONLY, S, CELLS, PW>), grid, block, 0, s, q, out, c->g, c->ph, c->bt,
+        hipLaunchKernelGGL((k_prim<D, PRIM_ONLY, S, CELLS, CT>), grid, block, 0, s, q, out, c->g, c->ph, c->bt,
                            c->d_sc);
 }
 
 template <int D, int S, int CELLS>
 void launch_prim_s(bub_ctx *c, const double *q, double *out, int mode, hipStream_t s)
 {
-    if (pw_fast(c)) launch_prim_p<D, S, CELLS, true>(c, q, out, mode, s);
-    else launch_prim_p<D, S, CELLS, false>(c, q, out, mode, s);
+    switch (ct_of(c)) {
+    case CT_FIFTHS: launch_prim_p<D, S, CELLS, CT_FIFTHS>(c, q, out, mode, s); break;
+    case CT_TRANSFER: launch_prim_p<D, S, CELLS, CT_TRANSFER>(c, q, out, mode, s); break;
+    default: launch_prim_p<D, S, CELLS, CT_POLY>(c, q, out, mode, s); break;
+    }
 }
 
 template <int D>
@@ -199,10 +208,14 @@ int launch_stage_t(bub_ctx *c, StageArgs A, hipStream_t s)
     const dim3 grid(8 * A.nblk_per_xcd), block(TC::BLOCK);
     if (!pw_fast(c)) {
         if constexpr (V == 0) {
-            if (A.Pout) return BUB_EINVAL;   // (stage_fusable is false for the general power)
+            if (A.Pout) return BUB_EINVAL;   // (stage_fusable is false for these contents)
             long pr = prof_begin(c, BUB_K_STAGE, s);
-            hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF, false, false>), grid, block, 0, s,
-                               A, c->g, c->ph, c->bt);
+            if (ct_of(c) == CT_TRANSFER)
+                hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF, false, CT_TRANSFER>), grid,
+                                   block, 0, s, A, c->g, c->ph, c->bt);
+            else
+                hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF, false, CT_POLY>), grid, block,
+                                   0, s, A, c->g, c->ph, c->bt);
             prof_end(c, pr, s);
             return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
         }
@@ -210,11 +223,11 @@ int launch_stage_t(bub_ctx *c, StageArgs A, hipStream_t s)
     }
     long pr = prof_begin(c, BUB_K_STAGE, s);
     if (A.Pout)
-        hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF, true, true>), grid, block, 0, s, A,
-                           c->g, c->ph, c->bt);
+        hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF, true, CT_FIFTHS>), grid, block, 0, s,
+                           A, c->g, c->ph, c->bt);
     else
-        hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF, false, true>), grid, block, 0, s, A,
-                           c->g, c->ph, c->bt);
+        hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF, false, CT_FIFTHS>), grid, block, 0, s,
+                           A, c->g, c->ph, c->bt);
     prof_end(c, pr, s);
     return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
 }
@@ -230,8 +243,17 @@ template <int D, int S, int CELLS>
 void launch_bubble_s(bub_ctx *c, const BubbleArgs &B, hipStream_t s)
 {
     const dim3 grid((unsigned)((c->g.N + CELLS - 1) / CELLS)), block(S * CELLS);
-    if (pw_fast(c)) hipLaunchKernelGGL((k_bubble<D, S, CELLS, true>), grid, block, 0, s, B, c->g, c->ph, c->bt, c->d_sc);
-    else hipLaunchKernelGGL((k_bubble<D, S, CELLS, false>), grid, block, 0, s, B, c->g, c->ph, c->bt, c->d_sc);
+    switch (ct_of(c)) {
+    case CT_FIFTHS:
+        hipLaunchKernelGGL((k_bubble<D, S, CELLS, CT_FIFTHS>), grid, block, 0, s, B, c->g, c->ph, c->bt, c->d_sc);
+        break;
+    case CT_TRANSFER:
+        hipLaunchKernelGGL((k_bubble<D, S, CELLS, CT_TRANSFER>), grid, block, 0, s, B, c->g, c->ph, c->bt, c->d_sc);
+        break;
+    default:
+        hipLaunchKernelGGL((k_bubble<D, S, CELLS, CT_POLY>), grid, block, 0, s, B, c->g, c->ph, c->bt, c->d_sc);
+        break;
+    }
 }
 
 template <int D>
@@ -412,9 +434,11 @@ const char *bub_strerror(int code)
 
 namespace {
 
-// Bin table passed by value to the initialising kernel (no host memory to keep alive).
+// Bin table passed by value to the initialising kernel (no host memory to keep alive): BIN_FIELDS
+// arrays of nb values (r0, w, pg0, and the transfer contents' pb0, mv0, mg).
+constexpr int BIN_FIELDS = 6;
 struct BinTable {
-    double v[3 * NB_MAX];
+    double v[BIN_FIELDS * NB_MAX];
 };
 
 __global__ void k_ctx_init(double *bins, BinTable t, int n, Scalars *sc)
@@ -457,7 +481,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 void ctx_buffer_layout(int ndim, long long N, size_t *off_sc, size_t *off_P, size_t *off_P2, size_t *total)
 {
     const size_t pbytes = align256(sizeof(double) * (size_t)(ndim + 6) * (size_t)N);
-    *off_sc = align256(sizeof(double) * 3 * NB_MAX);
+    *off_sc = align256(sizeof(double) * BIN_FIELDS * NB_MAX);
     *off_P = *off_sc + align256(sizeof(Scalars));
     *off_P2 = slots_for(N) == 1 ? *off_P + pbytes : 0;
     *total = *off_P + pbytes + (*off_P2 ? pbytes : 0);
@@ -468,13 +492,15 @@ void ctx_finish(bub_ctx *c)
     c->bt.r0 = c->d_bins;
     c->bt.w = c->d_bins + c->nb;
     c->bt.pg0 = c->d_bins + 2 * c->nb;
+    c->bt.pb0 = c->d_bins + 3 * c->nb;
+    c->bt.mv0 = c->d_bins + 4 * c->nb;
+    c->bt.mg = c->d_bins + 5 * c->nb;
 }
 
 void bin_table(const bub_ctx *c, double *tab)
 {
-    std::memcpy(tab, c->h_r0, sizeof(double) * c->nb);
-    std::memcpy(tab + c->nb, c->h_w, sizeof(double) * c->nb);
-    std::memcpy(tab + 2 * c->nb, c->h_pg0, sizeof(double) * c->nb);
+    const double *f[BIN_FIELDS] = {c->h_r0, c->h_w, c->h_pg0, c->h_pb0, c->h_mv0, c->h_mg};
+    for (int k = 0; k < BIN_FIELDS; ++k) std::memcpy(tab + k * c->nb, f[k], sizeof(double) * c->nb);
 }
 
 // Validate the inputs and fill the host side of a context held by the caller (no allocation).
@@ -504,6 +530,14 @@ int ctx_fill(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, co
     if (opts->bubble_mode == BUB_BUBBLES_SPLIT && (!(opts->sub_rtol > 0.0) || opts->max_substeps < 1))
         return BUB_EINVAL;
     if (opts->viscous != 0 && opts->viscous != 1) return BUB_EINVAL;
+    if (opts->contents != BUB_CONTENTS_POLYTROPIC && opts->contents != BUB_CONTENTS_TRANSFER) return BUB_EINVAL;
+    const bool tr = opts->contents == BUB_CONTENTS_TRANSFER;
+    if (tr) {
+        const bub_transfer &t = opts->transfer;
+        if (!(t.gam_b > 1.0) || !(t.Rg > 0.0) || !(t.Rv > 0.0) || !(t.T0 > 0.0) || !(t.k_b >= 0.0) ||
+            !(t.D_v >= 0.0) || !(t.beta_T >= 0.0) || !(t.beta_c >= 0.0) || !(gas->pv < liq->p0))
+            return BUB_EINVAL;
+    }
 
     c->grid = *grid;
     c->liq = *liq;
@@ -514,13 +548,23 @@ int ctx_fill(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, co
     if (rc) return rc;
     c->ndim = grid->ndim;
     c->nb = bins->nb;
-    c->nvar = c->ndim + 3 + 2 * c->nb;
+    const int nf = tr ? 4 : 2;
+    c->nvar = c->ndim + 3 + nf * c->nb;
     c->nprim = c->ndim + 6;
     c->N = N;
     double m3 = 0.0;
+    const bub_transfer &t = opts->transfer;
     for (int i = 0; i < c->nb; ++i) {
         c->h_pg0[i] = liq->p0 + 2.0 * gas->sigma / c->h_r0[i] - gas->pv;
         m3 += c->h_w[i] * c->h_r0[i] * c->h_r0[i] * c->h_r0[i];
+        c->h_pb0[i] = c->h_mv0[i] = c->h_mg[i] = 0.0;
+        if (tr) {
+            // equilibrium: contents at the Laplace pressure, vapour saturated at T0, the rest gas at T0
+            const double V0 = FOUR_PI_3 * c->h_r0[i] * c->h_r0[i] * c->h_r0[i];
+            c->h_pb0[i] = liq->p0 + 2.0 * gas->sigma / c->h_r0[i];
+            c->h_mv0[i] = gas->pv * V0 / (t.Rv * t.T0);
+            c->h_mg[i] = (c->h_pb0[i] - gas->pv) * V0 / (t.Rg * t.T0);
+        }
     }
     if (hipGetDevice(&c->device) != hipSuccess) return BUB_EHIP;
     c->ph.gamma = liq->gamma;
@@ -533,6 +577,19 @@ int ctx_fill(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, co
     c->ph.mu4 = 4.0 * gas->mu;
     c->ph.p0 = liq->p0;
     c->ph.rho0 = liq->rho0;
+    if (tr) {
+        c->ph.g3 = 3.0 * t.gam_b;
+        c->ph.Rg = t.Rg;
+        c->ph.Rv = t.Rv;
+        c->ph.T0 = t.T0;
+        c->ph.pv = gas->pv;
+        c->ph.kh = (t.gam_b - 1.0) / t.gam_b * t.k_b;
+        c->ph.betaT = t.beta_T;
+        c->ph.dbc = t.D_v * t.beta_c;
+        c->ph.pvRg = gas->pv * t.Rg;
+        c->ph.RvT0 = t.Rv * t.T0;
+        c->ph.inv_RgRv2T0 = 1.0 / (t.Rg * t.Rv * t.Rv * t.T0);
+    }
     // 3 kappa = n / 5 for a whole n (kappa = 1, 1.4, 5/3, ...): the fifth-root power
     const double n5 = 5.0 * c->ph.kappa3;
     const long long n = std::llround(n5);
@@ -547,10 +604,9 @@ int ctx_fill(const bub_grid *grid, const bub_liquid *liq, const bub_gas *gas, co
         c->g.inv_dx[d] = d < grid->ndim ? 1.0 / grid->dx[d] : 0.0;
     }
     c->g.N = N;
-    c->bt.r0 = c->d_bins;
-    c->bt.w = c->d_bins + c->nb;
-    c->bt.pg0 = c->d_bins + 2 * c->nb;
+    ctx_finish(c);
     c->bt.nb = c->nb;
+    c->bt.nf = nf;
     c->bt.m3_eq = m3;
     return BUB_OK;
 }
@@ -584,16 +640,16 @@ int bub_ctx_create(const bub_grid *grid, const bub_liquid *liq, const bub_gas *g
     if (rc) return rc;
     size_t pbytes = sizeof(double) * (size_t)c->nprim * (size_t)c->N;
     c->owns = true;
-    if (hipMalloc(&c->d_bins, sizeof(double) * 3 * NB_MAX) != hipSuccess ||
+    if (hipMalloc(&c->d_bins, sizeof(double) * BIN_FIELDS * NB_MAX) != hipSuccess ||
         hipMalloc(&c->d_P, pbytes) != hipSuccess || hipMalloc(&c->d_sc, sizeof(Scalars)) != hipSuccess ||
         (slots_for(c->N) == 1 && hipMalloc(&c->d_P2, pbytes) != hipSuccess)) {
         bub_ctx_destroy(c);
         return BUB_ENOMEM;
     }
-    double tab[3 * NB_MAX];
+    double tab[BIN_FIELDS * NB_MAX];
     bin_table(c, tab);
     Scalars zero{};
-    if (hipMemcpy(c->d_bins, tab, sizeof(double) * 3 * c->nb, hipMemcpyHostToDevice) != hipSuccess ||
+    if (hipMemcpy(c->d_bins, tab, sizeof(double) * BIN_FIELDS * c->nb, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_sc, &zero, sizeof(Scalars), hipMemcpyHostToDevice) != hipSuccess) {
         bub_ctx_destroy(c);
         return BUB_EHIP;
@@ -637,7 +693,7 @@ int bub_ctx_create_on(const bub_grid *grid, const bub_liquid *liq, const bub_gas
     c->d_P2 = off_P2 ? (double *)(base + off_P2) : nullptr;
     BinTable t{};
     bin_table(c, t.v);
-    hipLaunchKernelGGL(k_ctx_init, dim3(1), dim3(64), 0, (hipStream_t)stream, c->d_bins, t, 3 * c->nb, c->d_sc);
+    hipLaunchKernelGGL(k_ctx_init, dim3(1), dim3(64), 0, (hipStream_t)stream, c->d_bins, t, BIN_FIELDS * c->nb, c->d_sc);
     if (hipGetLastError() != hipSuccess) {
         delete c;
         return BUB_EHIP;
@@ -835,6 +891,7 @@ namespace {
 int el_grid(const bub_ctx *c, ElGrid *g)
 {
     if (c->ndim != 3) return BUB_EUNSUPPORTED;
+    if (c->opts.contents != BUB_CONTENTS_POLYTROPIC) return BUB_EUNSUPPORTED;   // Lagrangian bubbles: polytropic
     if (c->grid.dx[1] != c->grid.dx[0] || c->grid.dx[2] != c->grid.dx[0]) return BUB_EUNSUPPORTED;
     for (int d = 0; d < 3; ++d) {
         g->n[d] = c->g.n[d];

@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(S * CELLS) k_prim_group(const BatchMember *__r
     __syncthreads();
     const int j = list_find(L, blockIdx.x);
     const BatchMember &m = tab[L->member[j]];
-    prim_block<D, MODE, S, CELLS, true>(member_state(m, which), m.P, m.g, m.ph, m.bt, m.sc, blockIdx.x - L->start[j], s_pp);
+    prim_block<D, MODE, S, CELLS, CT_FIFTHS>(member_state(m, which), m.P, m.g, m.ph, m.bt, m.sc, blockIdx.x - L->start[j], s_pp);
 }
 
 // The step of every listed member from its wave-speed maxima: one block of WMAX_SLOTS threads each.
@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(S * CELLS) k_bubble_group(const BatchMember *_
     A.tau_scale = 0.5;
     A.rtol = m.rtol;
     A.max_substeps = m.max_substeps;
-    bubble_block<D, S, CELLS, true>(A, m.g, m.ph, m.bt, m.sc, blockIdx.x - L->start[j]);
+    bubble_block<D, S, CELLS, CT_FIFTHS>(A, m.g, m.ph, m.bt, m.sc, blockIdx.x - L->start[j]);
 }
 
 // RK stage k (1, 2 or 3) of every listed member; list offsets count stage items.  Blocks are mapped
@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(S * CELLS) k_bubble_group(const BatchMember *_
 template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((D <= 2 && sizeof(TF) == 4) ? 5 : 1))) k_stage_group(const BatchMember *__restrict__ tab, const LaunchList *__restrict__ L, int stage, int nblk_per_xcd)
 {
-    BUB_STAGE_SHARED(D, TX_, TY_, TZ_, BLOCK, TF)
+    BUB_STAGE_SHARED(D, TX_, TY_, TZ_, BLOCK, TF, 2)
     const int b = blockIdx.x;
     const int item = (b & 7) * nblk_per_xcd + (b >> 3);
     if (item >= L->start[L->count]) return;
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((D <
     } else {
         A.qk = m.w2; A.qn = m.q; A.qo = m.q; A.a = 1.0 / 3.0; A.b = 2.0 / 3.0;
     }
-    stage_item<D, TX_, TY_, TZ_, BLOCK, TF, false, true>(A, m.g, m.ph, m.bt, item - L->start[j], s_coef, s_scr, s_flag,
+    stage_item<D, TX_, TY_, TZ_, BLOCK, TF, false, CT_FIFTHS>(A, m.g, m.ph, m.bt, item - L->start[j], s_coef, s_scr, s_flag,
                                                    s_out, s_pp);
 }
 

@@ -23,7 +23,8 @@ struct bub_ctx {
     int ndim = 0, nb = 0, nvar = 0, nprim = 0;
     long long N = 0;
     double h_r0[bub::NB_MAX]{}, h_w[bub::NB_MAX]{}, h_pg0[bub::NB_MAX]{};
-    double *d_bins = nullptr;    // [3][nb]: r0, w, pg0
+    double h_pb0[bub::NB_MAX]{}, h_mv0[bub::NB_MAX]{}, h_mg[bub::NB_MAX]{};   // transfer contents
+    double *d_bins = nullptr;    // [BIN_FIELDS][nb]: r0, w, pg0, pb0, mv0, mg
     double *d_P = nullptr;       // [nprim][N] primitive scratch
     double *d_P2 = nullptr;      // second primitive scratch of the fused stages (grids of 2^19 cells or more)
     bub::Scalars *d_sc = nullptr;

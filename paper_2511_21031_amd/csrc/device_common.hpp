@@ -1,8 +1,9 @@
 // Device building blocks of the ensemble-averaged RHS stage (gfx950).
 //
 // Every formula here follows the paper: stiffened-gas liquid (eq. eos_liquid),
-// mixture pressure (eq. e:pressure), Keller--Miksis with polytropic contents
-// (eq. keller_miksis), WENO5 reconstruction and HLLC fluxes (Sec. 3).  The
+// mixture pressure (eq. e:pressure), Keller--Miksis with polytropic or transfer
+// contents (eq. keller_miksis, eq. massVaporRate and the contents-pressure
+// equation), WENO5 reconstruction and HLLC fluxes (Sec. 3).  The
 // arithmetic is arranged for the GPU (one reciprocal per WENO weight set,
 // products instead of divisions where the value is unchanged), so results
 // agree with a plain evaluation to rounding, not bit for bit.
@@ -15,6 +16,12 @@ namespace bub {
 
 constexpr int NB_MAX = 63;
 constexpr double FOUR_PI_3 = 4.18879020478639098461685784437;  // 4 pi / 3
+constexpr double FOUR_PI = 12.5663706143591729538505735331;    // 4 pi
+
+// Bubble contents of a context, compiled into the kernels that need them: polytropic gas with the
+// general power, polytropic gas with the fifth-root power (3 kappa a whole number of fifths), or gas and
+// vapour with heat and vapour transfer at the wall (four state fields per bin instead of two).
+enum Contents : int { CT_POLY = 0, CT_FIFTHS = 1, CT_TRANSFER = 2 };
 
 // Physical constants, passed by value (kernel argument segment -> SGPRs).
 struct Phys {
@@ -22,6 +29,9 @@ struct Phys {
     double kappa3, sigma2, mu4;               // 3 kappa, 2 sigma, 4 mu
     double p0, rho0;
     int pw_c, pw_d;   // 3 kappa = (5 pw_c - pw_d) / 5 for the fifth-root power (pw_c = 0: the general one)
+    // transfer contents (CT_TRANSFER): 3 gamma_b, gas constants, wall temperature and vapour pressure,
+    // the heat coefficient (gamma_b - 1)/gamma_b k_b beta_T, D_v beta_c, and the products used below
+    double g3, Rg, Rv, T0, pv, kh, betaT, dbc, pvRg, RvT0, inv_RgRv2T0;
 };
 
 // Grid: cells per direction, boundary kind per direction (0 periodic,
@@ -33,10 +43,13 @@ struct Grid {
     long long N;
 };
 
-// Bin table in device memory: r0[nb], w[nb], pg0[nb].
+// Bin table in device memory: r0[nb], w[nb], pg0[nb]; with transfer contents also the equilibrium
+// contents pressure pb0[nb], vapour mass mv0[nb] and the gas mass mg[nb] of one bubble of each bin.
 struct Bins {
     const double *r0, *w, *pg0;
+    const double *pb0, *mv0, *mg;
     int nb;
+    int nf;        // state fields per bin: 2 (n R, n Rdot) or 4 (and n p_b, n m_v)
     double m3_eq;  // sum w r0^3
 };
 
@@ -309,6 +322,42 @@ __device__ inline double km_rddot_t(const Phys &ph, double R, double V, double r
     double pb = pg0 * kpow<PW>(r0 * iR, ph, C);
     double pbw = pb - ph.mu4 * V * iR - ph.sigma2 * iR;
     double dpbw = (-ph.kappa3 * pb * V + ph.mu4 * V * V * iR + ph.sigma2 * V * iR) * iR;
+    double irc = irho * ic;
+    double num = (1.0 + V * ic) * (pbw - pinf) * irho + R * dpbw * irc - 1.5 * V * V * (1.0 - V * ic * (1.0 / 3.0));
+    double den = R * (1.0 - V * ic) + ph.mu4 * irc;
+    return num * frcp(den);
+}
+
+// Transfer contents of one bubble (Sec. 2, eq. massVaporRate and the contents-pressure equation): the
+// rates of p_b and m_v for radius R, wall velocity V, pressure p and vapour mass m, gas mass mg.  The
+// contents are an ideal-gas mixture at uniform p with mean temperature Tbar = p V_b/(mg Rg + m Rv); the
+// wall keeps the liquid temperature T0 with its vapour saturated (partial pressure pv), so with
+// S = pv Rg + (p - pv) Rv its vapour mass fraction is chi_w = pv Rg / S and the factor rho_w/(1 - chi_w)
+// of the vapour flux is S^2 / (Rg Rv^2 T0 (p - pv)) (rho_w = S/(Rg Rv T0)).  Wall gradients: the transfer
+// coefficients times (wall value - bubble mean)/R.
+__device__ inline void contents_rates(const Phys &ph, double R, double V, double p, double m, double mg,
+                                      double &pdot, double &mdot)
+{
+    const double iR = frcp(R);
+    const double Tbar = p * (FOUR_PI_3 * R * R * R) / (mg * ph.Rg + m * ph.Rv);
+    const double chibar = m / (m + mg);
+    const double S = ph.pvRg + (p - ph.pv) * ph.Rv;
+    const double iS = frcp(S);
+    const double chiw = ph.pvRg * iS;
+    const double flux = ph.dbc * (S * S * ph.inv_RgRv2T0) / (p - ph.pv) * (chiw - chibar) * iR;
+    const double dTdr = ph.betaT * (ph.T0 - Tbar) * iR;
+    pdot = ph.g3 * iR * (-V * p + ph.RvT0 * flux + ph.kh * dTdr);
+    mdot = FOUR_PI * R * R * flux;
+}
+
+// Keller--Miksis wall acceleration for contents of pressure p changing at the rate pdot (transfer
+// contents); the R-ddot part of d(p_bw)/dt is moved to the left as above.
+__device__ inline double km_rddot_pb(const Phys &ph, double R, double V, double p, double pdot, double pinf,
+                                     double irho, double ic)
+{
+    double iR = frcp(R);
+    double pbw = p - ph.mu4 * V * iR - ph.sigma2 * iR;
+    double dpbw = pdot + (ph.mu4 * V * V * iR + ph.sigma2 * V * iR) * iR;
     double irc = irho * ic;
     double num = (1.0 + V * ic) * (pbw - pinf) * irho + R * dpbw * irc - 1.5 * V * V * (1.0 - V * ic * (1.0 / 3.0));
     double den = R * (1.0 - V * ic) + ph.mu4 * irc;

@@ -34,8 +34,9 @@ constexpr int PRIM_SLOTS = 8;   // threads per cell in the primitive pass
 // Bin sums of the primitive pass in the conserved variables x = nR, y = nRdot.  With R = x/n and
 // Rdot = y/n every moment is a power of n times a sum that does not involve n, including the
 // contents term
-//   R^3 p_b(R) = p_g0 R^3 (R0/R)^(3 kappa) = n^(3 kappa - 3) p_g0 x^3 (R0/x)^(3 kappa).
-// bad = the first bin with x <= 0 (n > 0, so R_i has the sign of x), or nb.
+//   R^3 p_b(R) = p_g0 R^3 (R0/R)^(3 kappa) = n^(3 kappa - 3) p_g0 x^3 (R0/x)^(3 kappa),
+// or, for transfer contents with z = n p_b in the state, R^3 p_b = n^-4 x^3 z.
+// bad = the first bin with x <= 0 (n > 0, so R_i has the sign of x) or z <= 0, or nb.
 struct BinSums {
     double s3 = 0.0, s2 = 0.0, s21 = 0.0, s32 = 0.0, sp = 0.0;
     int bad;
@@ -59,7 +60,21 @@ __device__ __forceinline__ void bin_add(BinSums &r, int i, double x, double y, d
     r.sp = fma(wx3 * pg0, kpow<PW>(r0 * frcp(x), ph, C), r.sp);
 }
 
-template <int D, bool PW>
+// One bin's terms of transfer contents (z = n p_b).
+__device__ __forceinline__ void bin_add_tr(BinSums &r, int i, double x, double y, double z, double w, int nb)
+{
+#pragma clang fp contract(off)
+    if (!(x > 0.0 && z > 0.0) && r.bad == nb) r.bad = i;
+    const double x2 = x * x, x3 = x2 * x;
+    const double wx2 = w * x2, wx3 = w * x3;
+    r.s3 = fma(w, x3, r.s3);
+    r.s2 = fma(w, x2, r.s2);
+    r.s21 = fma(wx2, y, r.s21);
+    r.s32 = fma(wx3 * y, y, r.s32);
+    r.sp = fma(wx3, z, r.sp);
+}
+
+template <int D, int CT>
 __device__ __forceinline__ BinSums bin_sums(const double *__restrict__ q, const Phys &ph, const Bins &bins,
                                             long long N, long long c, int first, int stride,
                                             const double *__restrict__ C)
@@ -67,6 +82,13 @@ __device__ __forceinline__ BinSums bin_sums(const double *__restrict__ q, const 
     const int nb = bins.nb, iNR = D + 3, iNV = D + 3 + nb;
     BinSums r;
     r.bad = nb;
+    if constexpr (CT == CT_TRANSFER) {
+        const int iNP = D + 3 + 2 * nb;
+        for (int i = first; i < nb; i += stride)
+            bin_add_tr(r, i, q[(iNR + i) * N + c], q[(iNV + i) * N + c], q[(iNP + i) * N + c], bins.w[i], nb);
+        return r;
+    }
+    constexpr bool PW = CT == CT_FIFTHS;
     // The pass is bound by the latency of the bin loads: four bins' values are loaded together,
     // then summed one bin at a time in bin order (scheduling barriers keep the loads grouped and
     // the four sums apart, so registers stay few).
@@ -128,6 +150,7 @@ struct CellBins {
     double n, B, Sa, M3, M2d, Mp, Mk;
 };
 
+template <int CT>
 __device__ __forceinline__ CellBins cell_bins(double rho, double a, const BinSums &t, const Phys &ph, const Bins &bins)
 {
 #pragma clang fp contract(off)
@@ -139,7 +162,8 @@ __device__ __forceinline__ CellBins cell_bins(double rho, double a, const BinSum
         o.M3 = t.s3 * in3;
         o.M2d = t.s21 * in3;
         o.Mk = t.s32 * in3 * in2;
-        o.Mp = exp2((ph.kappa3 - 3.0) * log2(o.n)) * t.sp - ph.mu4 * o.M2d - ph.sigma2 * t.s2 * in2;
+        if constexpr (CT == CT_TRANSFER) o.Mp = t.sp * (in3 * in) - ph.mu4 * o.M2d - ph.sigma2 * t.s2 * in2;
+        else o.Mp = exp2((ph.kappa3 - 3.0) * log2(o.n)) * t.sp - ph.mu4 * o.M2d - ph.sigma2 * t.s2 * in2;
         const double iM3 = frcp(o.M3);
         o.B = (o.Mp - rho * o.Mk) * iM3;
         o.Sa = 3.0 * a * o.M2d * iM3;
@@ -154,7 +178,7 @@ __device__ __forceinline__ CellBins cell_bins(double rho, double a, const BinSum
 
 // The rest of one cell of the primitive pass, given its bin sums: primitives, moments,
 // B, the alpha source, error checks; returns max_d (|u_d| + c)/dx_d in CFL mode (0 otherwise).
-template <int D, int MODE>
+template <int D, int MODE, int CT>
 __device__ __forceinline__ double prim_finish(const double *__restrict__ q, double *__restrict__ out, const Grid &g,
                                               const Phys &ph, const Bins &bins, Scalars *sc, long long c,
                                               const BinSums &t)
@@ -168,7 +192,7 @@ __device__ __forceinline__ double prim_finish(const double *__restrict__ q, doub
     const double E = q[(D + 1) * N + c];
     const double a = q[(D + 2) * N + c];
     const CellCore<D> k = cell_core<D>(rho, mom, E, a, ph);
-    const CellBins m = cell_bins(rho, a, t, ph, bins);
+    const CellBins m = cell_bins<CT>(rho, a, t, ph, bins);
     bool bad = k.bad || !(m.B == m.B) || !(m.n == m.n);
     const bool negr = a > 0.0 && t.bad < nb;
     if (negr) raise_error(sc, E_NEGR, c, t.bad);   // a negative radius also makes B non-finite
@@ -211,7 +235,7 @@ __device__ inline void cfl_reduce(double wmax, Scalars *sc) { wmax_post(wmax, sc
 // grids, which fill the chip on cells alone).
 // Block `blk` of the pass (cells blk*CELLS ..); every thread of the workgroup calls it.  s_pp: the
 // power's constant table in LDS, filled by the caller before a barrier.
-template <int D, int MODE, int S, int CELLS, bool PW>
+template <int D, int MODE, int S, int CELLS, int CT>
 __device__ __forceinline__ void prim_block(const double *__restrict__ q, double *__restrict__ out, const Grid &g,
                                            const Phys &ph, const Bins &bins, Scalars *sc, long long blk,
                                            const double *__restrict__ s_pp)
@@ -225,8 +249,8 @@ __device__ __forceinline__ void prim_block(const double *__restrict__ q, double 
     if constexpr (S == 1) {
         BinSums p;
         p.bad = bins.nb;
-        if (live && q[(D + 2) * N + c] > 0.0) p = bin_sums<D, PW>(q, ph, bins, N, c, 0, 1, s_pp);
-        if (live) wmax = prim_finish<D, MODE>(q, out, g, ph, bins, sc, c, p);
+        if (live && q[(D + 2) * N + c] > 0.0) p = bin_sums<D, CT>(q, ph, bins, N, c, 0, 1, s_pp);
+        if (live) wmax = prim_finish<D, MODE, CT>(q, out, g, ph, bins, sc, c, p);
     } else {
         __shared__ double s_sum[5][S][CELLS];
         __shared__ int s_bad[S][CELLS];
@@ -235,7 +259,7 @@ __device__ __forceinline__ void prim_block(const double *__restrict__ q, double 
         __syncthreads();
         BinSums p;
         p.bad = bins.nb;
-        if (live && q[(D + 2) * N + c] > 0.0) p = bin_sums<D, PW>(q, ph, bins, N, c, slot, S, s_pp);
+        if (live && q[(D + 2) * N + c] > 0.0) p = bin_sums<D, CT>(q, ph, bins, N, c, slot, S, s_pp);
         s_sum[0][slot][cl] = p.s3;
         s_sum[1][slot][cl] = p.s2;
         s_sum[2][slot][cl] = p.s21;
@@ -257,20 +281,20 @@ __device__ __forceinline__ void prim_block(const double *__restrict__ q, double 
                 t.sp += s_sum[4][k][cl];
                 t.bad = s_bad[k][cl] < t.bad ? s_bad[k][cl] : t.bad;
             }
-            wmax = prim_finish<D, MODE>(q, out, g, ph, bins, sc, c, t);
+            wmax = prim_finish<D, MODE, CT>(q, out, g, ph, bins, sc, c, t);
         }
     }
     if (MODE == PRIM_CFL) cfl_reduce(wmax, sc);
 }
 
-template <int D, int MODE, int S, int CELLS, bool PW>
+template <int D, int MODE, int S, int CELLS, int CT>
 __global__ void __launch_bounds__(S * CELLS) k_prim(const double *__restrict__ q, double *__restrict__ out,
                                                     Grid g, Phys ph, Bins bins, Scalars *sc)
 {
     __shared__ double s_pp[PPOW_N];   // constants of the polytropic power
     if (threadIdx.x < PPOW_N) s_pp[threadIdx.x] = PPOW_TABLE[threadIdx.x];
     __syncthreads();
-    prim_block<D, MODE, S, CELLS, PW>(q, out, g, ph, bins, sc, blockIdx.x, s_pp);
+    prim_block<D, MODE, S, CELLS, CT>(q, out, g, ph, bins, sc, blockIdx.x, s_pp);
 }
 
 // Threads per cell for a grid of N cells: enough to give about 2^19 threads, at most PRIM_SLOTS.
@@ -307,6 +331,10 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ prim, d
         for (int i = 0; i < nb; ++i) {
             q[(D + 3 + i) * N + c] = n * bins.r0[i];
             q[(D + 3 + nb + i) * N + c] = 0.0;
+            if (bins.nf == 4) {
+                q[(D + 3 + 2 * nb + i) * N + c] = n * bins.pb0[i];
+                q[(D + 3 + 3 * nb + i) * N + c] = n * bins.mv0[i];
+            }
         }
     }
 }

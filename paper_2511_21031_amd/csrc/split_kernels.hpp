@@ -1,7 +1,7 @@
 // Bubble half-step of the Strang splitting (Sec. 3) for gfx950.
 //
-// Every (R, Rdot) pair is advanced over tau by Keller--Miksis with its cell's
-// liquid state frozen, using the embedded SSP-RK3 / Heun-RK2 pair that shares
+// Every (R, Rdot) pair (with transfer contents: (R, Rdot, p_b, m_v)) is
+// advanced over tau by Keller--Miksis with its cell's liquid state frozen, using the embedded SSP-RK3 / Heun-RK2 pair that shares
 // the first two stages.  A workgroup owns consecutive cells and gives each cell
 // S threads: the lanes of a wave hold neighbouring cells of the same bin subset
 // (bins slot, slot + S, ...), whose sub-step counts are similar, so divergence
@@ -65,13 +65,71 @@ __device__ inline int bubble_bin(const Phys &ph, double &y0, double &y1, double 
     return accepted;
 }
 
+// The same pair for transfer contents, y = (R, Rdot, p_b, m_v) of one bubble of gas mass mg; the error
+// norm adds |dp_b|/|p_b| and |dm_v|/(|m_v| + mg), and a sub-step needs R > 0 and p_b > 0.
+__device__ inline void tr_rates(const Phys &ph, double mg, double pl, double irhol, double ic, const double *y,
+                                double *f)
+{
+    double pdot, mdot;
+    contents_rates(ph, y[0], y[1], y[2], y[3], mg, pdot, mdot);
+    f[0] = y[1];
+    f[1] = km_rddot_pb(ph, y[0], y[1], y[2], pdot, pl, irhol, ic);
+    f[2] = pdot;
+    f[3] = mdot;
+}
+
+__device__ inline int bubble_bin_tr(const Phys &ph, double *y, double mg, double pl, double irhol, double ic,
+                                    double tau, double rtol, double vfloor, int max_substeps, Scalars *sc,
+                                    long long c, int i)
+{
+    double t = 0.0, h = tau;
+    int accepted = 0, attempts = 0;
+    while (t < tau) {
+        if (attempts >= max_substeps) {
+            raise_error(sc, E_SUBSTEP, c, i);
+            break;
+        }
+        ++attempts;
+        if (h > tau - t) h = tau - t;
+        double k1[4], k2[4], k3[4], a[4], b[4], e[4], nn[4];
+        tr_rates(ph, mg, pl, irhol, ic, y, k1);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[j] = y[j] + h * k1[j];
+        tr_rates(ph, mg, pl, irhol, ic, a, k2);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            b[j] = 0.75 * y[j] + 0.25 * (a[j] + h * k2[j]);
+            e[j] = y[j] + 0.5 * h * (k1[j] + k2[j]);
+        }
+        tr_rates(ph, mg, pl, irhol, ic, b, k3);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) nn[j] = y[j] * (1.0 / 3.0) + (2.0 / 3.0) * (b[j] + h * k3[j]);
+        double err = dmax(fabs(nn[0] - e[0]) / fabs(nn[0]), fabs(nn[1] - e[1]) / dmax(fabs(nn[1]), vfloor));
+        err = dmax(err, fabs(nn[2] - e[2]) / fabs(nn[2]));
+        err = dmax(err, fabs(nn[3] - e[3]) / (fabs(nn[3]) + mg));
+        if (!(err == err)) err = INFINITY;
+        const bool pos = nn[0] > 0.0 && nn[2] > 0.0;
+        if (err <= rtol && pos) {
+            t += h;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) y[j] = nn[j];
+            ++accepted;
+        }
+        double fac = err > 0.0 ? 0.9 * pow(rtol / err, 1.0 / 3.0) : 4.0;
+        if (!pos) fac = 0.25;
+        fac = dmin(4.0, dmax(0.25, fac));
+        h *= fac;
+    }
+    return accepted;
+}
+
 // One bubble half-step over the whole grid; grid = ceil(N / CELLS) workgroups of CELLS * S
 // threads (S threads per cell; S = 1 walks all bins of a cell in one thread).  With S > 1 the
 // slots first pool sum w (nR)^3 for n (one barrier), then each advances its bins, posts its part
 // of sum w R^3 before and after, and bumps the cell's LDS counter; the slot that arrives last
 // updates alpha, so waves whose bins need fewer sub-steps leave without waiting.
 // Block `blk` of the half-step (cells blk*CELLS ..); every thread of the workgroup calls it.
-template <int D, int S, int CELLS, bool PW>
+template <int D, int S, int CELLS, int CT>
 __device__ __forceinline__ void bubble_block(const BubbleArgs &A, const Grid &g, const Phys &ph, const Bins &bins,
                                              Scalars *sc, long long blk)
 {
@@ -134,8 +192,19 @@ __device__ __forceinline__ void bubble_block(const BubbleArgs &A, const Grid &g,
             double y1 = q[(iNV + i) * N + c] * in;
             const double wi = bins.w[i];
             m3_old += wi * y0 * y0 * y0;
-            int acc = bubble_bin<PW>(ph, y0, y1, bins.r0[i], bins.pg0[i], pl, irhol, ic, tau, A.rtol, vfloor,
-                                 A.max_substeps, sc, c, i);
+            int acc;
+            if constexpr (CT == CT_TRANSFER) {
+                const int iNP = D + 3 + 2 * nb, iNM = D + 3 + 3 * nb;
+                double y[4] = {y0, y1, q[(iNP + i) * N + c] * in, q[(iNM + i) * N + c] * in};
+                acc = bubble_bin_tr(ph, y, bins.mg[i], pl, irhol, ic, tau, A.rtol, vfloor, A.max_substeps, sc, c, i);
+                y0 = y[0];
+                y1 = y[1];
+                q[(iNP + i) * N + c] = n * y[2];
+                q[(iNM + i) * N + c] = n * y[3];
+            } else {
+                acc = bubble_bin<CT == CT_FIFTHS>(ph, y0, y1, bins.r0[i], bins.pg0[i], pl, irhol, ic, tau, A.rtol,
+                                                  vfloor, A.max_substeps, sc, c, i);
+            }
             q[(iNR + i) * N + c] = n * y0;
             q[(iNV + i) * N + c] = n * y1;
             m3_new += wi * y0 * y0 * y0;
@@ -164,10 +233,10 @@ __device__ __forceinline__ void bubble_block(const BubbleArgs &A, const Grid &g,
     }
 }
 
-template <int D, int S, int CELLS, bool PW>
+template <int D, int S, int CELLS, int CT>
 __global__ void __launch_bounds__(S * CELLS) k_bubble(BubbleArgs A, Grid g, Phys ph, Bins bins, Scalars *sc)
 {
-    bubble_block<D, S, CELLS, PW>(A, g, ph, bins, sc, blockIdx.x);
+    bubble_block<D, S, CELLS, CT>(A, g, ph, bins, sc, blockIdx.x);
 }
 
 }  // namespace bub

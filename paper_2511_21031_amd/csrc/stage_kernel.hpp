@@ -125,20 +125,21 @@ struct StageArgs {
     Scalars *sc;        // error word and wave-speed maxima of the context
 };
 
-// LDS needs of one tile: coef[F] and scr[SCR] of TF, flag[F] bytes.
-template <int D, int TX_, int TY_, int TZ_, typename TF>
+// LDS needs of one tile: coef[F] and scr[SCR] of TF, flag[F] bytes.  NF: state fields per bin (2, or 4
+// for transfer contents), each with a line array and a face array.
+template <int D, int TX_, int TY_, int TZ_, typename TF, int NF = 2>
 struct StageLds {
     using G = Geo<D, TX_, TY_, TZ_>;
     // line arrays of R and Rdot are LP apart, a multiple of 64 elements, so one paired LDS
     // access (64-element stride form) serves both
     static constexpr int LP = (G::L + 63) / 64 * 64;
-    static constexpr int SCR = (G::NCF * G::F > 2 * LP + 2 * G::F) ? G::NCF * G::F : 2 * LP + 2 * G::F;
+    static constexpr int SCR = (G::NCF * G::F > NF * LP + NF * G::F) ? G::NCF * G::F : NF * LP + NF * G::F;
     static constexpr int BYTES = (G::F + SCR) * (int)sizeof(TF) + G::F;
 };
 
 // The work of one tile (every thread of the workgroup calls it).  FUSE: the epilogue carries the
 // primitive pass of the state it writes (A.Pout, A.cfl).
-template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF, bool FUSE, bool PW>
+template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF, bool FUSE, int CT>
 // Bins b0 <= ib < b1 are this workgroup's; core_out: it also writes the mixture variables
 // (exactly one workgroup per tile does).
 __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, const Phys &ph, const Bins &bins,
@@ -148,6 +149,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
 {
     using G = Geo<D, TX_, TY_, TZ_>;
     constexpr int T = G::T, F = G::F, C = G::C, NC = G::NC, NCF = G::NCF, L = G::L;
+    constexpr bool TR = CT == CT_TRANSFER;   // transfer contents: n p_b and n m_v per bin as well
+    constexpr bool PW = CT == CT_FIFTHS;
+    static_assert(!(TR && FUSE), "the fused epilogue takes polytropic contents");
     constexpr int CPT = (C + BLOCK - 1) / BLOCK;  // cross cells staged per thread
     const int tx = tile % A.ntile[0];
     const int ty = (tile / A.ntile[0]) % A.ntile[1];
@@ -289,13 +293,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
     if (D > 2) core_faces(std::integral_constant<int, (D > 2 ? 2 : 0)>{});
 
     // first bin's global loads go out while the core faces finish
-    const int iNR = D + 3, iNV = D + 3 + nb;
+    const int iNR = D + 3, iNV = D + 3 + nb, iNP = D + 3 + 2 * nb, iNM = D + 3 + 3 * nb;
     double pre_r[CPT], pre_v[CPT];
+    [[maybe_unused]] double pre_p[TR ? CPT : 1], pre_m[TR ? CPT : 1];
 #pragma unroll
     for (int r = 0; r < CPT; ++r) {
         bool ok = tid + r * BLOCK < C;
         pre_r[r] = ok ? A.qk[(long long)(iNR + b0) * N + st_g[r]] : 0.0;
         pre_v[r] = ok ? A.qk[(long long)(iNV + b0) * N + st_g[r]] : 0.0;
+        if constexpr (TR) {
+            pre_p[r] = ok ? A.qk[(long long)(iNP + b0) * N + st_g[r]] : 0.0;
+            pre_m[r] = ok ? A.qk[(long long)(iNM + b0) * N + st_g[r]] : 0.0;
+        }
     }
     __syncthreads();
 
@@ -379,28 +388,47 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
     const bool own_un = active && !A.rhs_mode && A.a != 0.0;
     double pre_nr = own_un ? A.qn[(long long)(iNR + b0) * N + gc] : 0.0;
     double pre_nv = own_un ? A.qn[(long long)(iNV + b0) * N + gc] : 0.0;
-    constexpr int LP = StageLds<D, TX_, TY_, TZ_, TF>::LP;
-    TF *s_R = s_scr, *s_V = s_scr + LP, *s_fR = s_scr + 2 * LP, *s_fV = s_scr + 2 * LP + F;
+    [[maybe_unused]] double pre_np = 0.0, pre_nm = 0.0;
+    if constexpr (TR) {
+        pre_np = own_un ? A.qn[(long long)(iNP + b0) * N + gc] : 0.0;
+        pre_nm = own_un ? A.qn[(long long)(iNM + b0) * N + gc] : 0.0;
+    }
+    constexpr int NF = TR ? 4 : 2;
+    constexpr int LP = StageLds<D, TX_, TY_, TZ_, TF, NF>::LP;
+    TF *s_R = s_scr, *s_V = s_scr + LP, *s_fR = s_scr + NF * LP, *s_fV = s_scr + NF * LP + F;
+    [[maybe_unused]] TF *s_P = s_scr + 2 * LP, *s_M = s_scr + 3 * LP;
+    [[maybe_unused]] TF *s_fP = s_scr + NF * LP + 2 * F, *s_fM = s_scr + NF * LP + 3 * F;
     // In 3D the owned cell's two results of a bin wait in this thread's own s_out slots and go
     // to HBM one bin late, ahead of the next bin's loads, so that the wait for those loads at
     // the next staging does not also wait for stores issued just before it (measured: 1-3 %
     // faster in 3D; in 2D the extra registers cost a wave per SIMD, so it stores at once).
-    constexpr bool DEFER = D == 3;
+    constexpr bool DEFER = D == 3 && !TR;
     for (int ib = b0; ib < b1; ++ib) {
         const double r0 = bins.r0[ib], pg0 = bins.pg0[ib];
         const double own_r = pre_r[0], own_v = pre_v[0], own_nr = pre_nr, own_nv = pre_nv;
+        [[maybe_unused]] const double own_p = TR ? pre_p[0] : 0.0, own_m = TR ? pre_m[0] : 0.0;
+        [[maybe_unused]] const double own_np = pre_np, own_nm = pre_nm;
 #pragma unroll
         for (int r = 0; r < CPT; ++r) {
             if (tid + r * BLOCK < C) {
                 double in = st_in[r];
                 TF Rv = (TF)(in > 0.0 ? pre_r[r] * in : r0);
                 TF Vv = (TF)(in > 0.0 ? pre_v[r] * in : 0.0);
+                [[maybe_unused]] TF Pv = TF(0), Mv = TF(0);
+                if constexpr (TR) {
+                    Pv = (TF)(in > 0.0 ? pre_p[r] * in : bins.pb0[ib]);
+                    Mv = (TF)(in > 0.0 ? pre_m[r] * in : bins.mv0[ib]);
+                }
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
                     int l = st_l[r][d];
                     if (l >= 0) {
                         s_R[l] = Rv;
                         s_V[l] = Vv;
+                        if constexpr (TR) {
+                            s_P[l] = Pv;
+                            s_M[l] = Mv;
+                        }
                     }
                 }
             }
@@ -414,12 +442,20 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
             if (own_un) {
                 pre_nr = A.qn[(long long)(iNR + ib + 1) * N + gc];
                 pre_nv = A.qn[(long long)(iNV + ib + 1) * N + gc];
+                if constexpr (TR) {
+                    pre_np = A.qn[(long long)(iNP + ib + 1) * N + gc];
+                    pre_nm = A.qn[(long long)(iNM + ib + 1) * N + gc];
+                }
             }
 #pragma unroll
             for (int r = 0; r < CPT; ++r) {
                 bool ok = tid + r * BLOCK < C;
                 pre_r[r] = ok ? A.qk[(long long)(iNR + ib + 1) * N + st_g[r]] : 0.0;
                 pre_v[r] = ok ? A.qk[(long long)(iNV + ib + 1) * N + st_g[r]] : 0.0;
+                if constexpr (TR) {
+                    pre_p[r] = ok ? A.qk[(long long)(iNP + ib + 1) * N + st_g[r]] : 0.0;
+                    pre_m[r] = ok ? A.qk[(long long)(iNM + ib + 1) * N + st_g[r]] : 0.0;
+                }
             }
         }
         auto bin_faces = [&](auto dtag) {
@@ -446,20 +482,45 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
                     vv[o] = s_V[st + o * sd];
                 }
                 TF RK, VK;
+                [[maybe_unused]] TF PK = TF(0), MK = TF(0);
+                [[maybe_unused]] TF pp[5], mm[5];
+                if constexpr (TR) {
+#pragma unroll
+                    for (int o = 0; o < 5; ++o) {
+                        pp[o] = s_P[st + o * sd];
+                        mm[o] = s_M[st + o * sd];
+                    }
+                }
                 if (fl & 2) {
                     RK = rr[2];
                     VK = vv[2];
+                    if constexpr (TR) {
+                        PK = pp[2];
+                        MK = mm[2];
+                    }
                 } else {
                     RK = weno5(rr[0], rr[1], rr[2], rr[3], rr[4]);
                     VK = weno5(vv[0], vv[1], vv[2], vv[3], vv[4]);
+                    if constexpr (TR) {
+                        PK = weno5(pp[0], pp[1], pp[2], pp[3], pp[4]);
+                        MK = weno5(mm[0], mm[1], mm[2], mm[3], mm[4]);
+                    }
                     if (!(RK > TF(0))) {
                         RK = rr[2];
                         VK = vv[2];
+                        if constexpr (TR) {
+                            PK = pp[2];
+                            MK = mm[2];
+                        }
                     }
                 }
                 TF cf = s_coef[slot];
                 s_fR[slot] = cf * RK;
                 s_fV[slot] = cf * VK;
+                if constexpr (TR) {
+                    s_fP[slot] = cf * PK;
+                    s_fM[slot] = cf * MK;
+                }
             }
         };
         bin_faces(std::integral_constant<int, 0>{});
@@ -468,27 +529,55 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
         __syncthreads();
         if (active) {
             TF LRf = TF(0), LVf = TF(0);
+            [[maybe_unused]] TF LPf = TF(0), LMf = TF(0);
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 LRf += (s_fR[flo[d]] - s_fR[fhi[d]]) * (TF)g.inv_dx[d];
                 LVf += (s_fV[flo[d]] - s_fV[fhi[d]]) * (TF)g.inv_dx[d];
+                if constexpr (TR) {
+                    LPf += (s_fP[flo[d]] - s_fP[fhi[d]]) * (TF)g.inv_dx[d];
+                    LMf += (s_fM[flo[d]] - s_fM[fhi[d]]) * (TF)g.inv_dx[d];
+                }
             }
             double LR = (double)LRf, LV = (double)LVf;
+            [[maybe_unused]] double LP_ = (double)LPf, LM_ = (double)LMf;
             const double xr0 = own_r, xv0 = own_v;   // u^(k) of bin ib at the owned cell
             if (A.sources && own_n > 0.0) {
                 // Keller--Miksis in FP64 from the FP64 state of the owned cell
                 double own_R = xr0 * own_in, own_V = xv0 * own_in;
                 LR += own_n * own_V;
-                LV += own_n * km_rddot_t<PW>(ph, own_R, own_V, r0, pg0, own_pl, own_irhol, own_ic, s_pp);
+                if constexpr (TR) {
+                    const double own_P = own_p * own_in, own_M = own_m * own_in;
+                    double pdot, mdot;
+                    contents_rates(ph, own_R, own_V, own_P, own_M, bins.mg[ib], pdot, mdot);
+                    LV += own_n * km_rddot_pb(ph, own_R, own_V, own_P, pdot, own_pl, own_irhol, own_ic);
+                    LP_ += own_n * pdot;
+                    LM_ += own_n * mdot;
+                } else {
+                    LV += own_n * km_rddot_t<PW>(ph, own_R, own_V, r0, pg0, own_pl, own_irhol, own_ic, s_pp);
+                }
             }
             double xr = LR, xv = LV;
+            [[maybe_unused]] double xp = LP_, xm = LM_;
             if (!A.rhs_mode) {
                 xr = A.b * (xr0 + dt * LR);
                 xv = A.b * (xv0 + dt * LV);
+                if constexpr (TR) {
+                    xp = A.b * (own_p + dt * LP_);
+                    xm = A.b * (own_m + dt * LM_);
+                }
                 if (A.a != 0.0) {
                     xr += A.a * own_nr;   // u^n of bin ib at the owned cell
                     xv += A.a * own_nv;
+                    if constexpr (TR) {
+                        xp += A.a * own_np;
+                        xm += A.a * own_nm;
+                    }
                 }
+            }
+            if constexpr (TR) {
+                A.qo[(long long)(iNP + ib) * N + gc] = xp;
+                A.qo[(long long)(iNM + ib) * N + gc] = xm;
             }
             if constexpr (fuse) bin_add<PW>(acc, ib, xr, xv, bins.w[ib], pg0, r0, nb, ph, s_pp);
             if constexpr (DEFER) {
@@ -509,7 +598,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
     if constexpr (fuse) {
         // the primitive pass of the new state for the owned cell (same arithmetic as k_prim)
         if (active) {
-            const CellBins m = cell_bins(new_rho, new_a, acc, ph, bins);
+            const CellBins m = cell_bins<CT>(new_rho, new_a, acc, ph, bins);
             A.Pout[PL<D>::N * N + gc] = m.n;
             A.Pout[PL<D>::B * N + gc] = m.B;
             A.Pout[PL<D>::SA * N + gc] = m.Sa;
@@ -522,19 +611,20 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
     __syncthreads();  // a following tile on this workgroup may reuse the LDS at once
 }
 
-// The unfused 1D and 2D kernels of the mixed form fit 96 VGPRs without spilling and run five waves
-// per SIMD (2D: 4 % faster stage than at four); the FP64 ones, and the fused ones, would spill.
+// The unfused 1D and 2D kernels of the mixed form with the fifth-root power fit 96 VGPRs without
+// spilling and run five waves per SIMD (2D: 4 % faster stage than at four); the FP64 ones, the fused
+// ones and those of the other contents would spill.
 // The LDS arrays of one stage workgroup, declared in the kernel that uses them.
-#define BUB_STAGE_SHARED(D, TX_, TY_, TZ_, BLOCK, TF)                                   \
+#define BUB_STAGE_SHARED(D, TX_, TY_, TZ_, BLOCK, TF, NF)                               \
     __shared__ TF s_coef[Geo<D, TX_, TY_, TZ_>::F];                                       \
-    __shared__ TF s_scr[StageLds<D, TX_, TY_, TZ_, TF>::SCR];                             \
+    __shared__ TF s_scr[StageLds<D, TX_, TY_, TZ_, TF, NF>::SCR];                         \
     __shared__ unsigned char s_flag[Geo<D, TX_, TY_, TZ_>::F];                            \
     __shared__ double s_out[D == 3 ? 2 * BLOCK : 1]; /* 3D: results stored one bin late */ \
     __shared__ double s_pp[PPOW_N];                  /* constants of the polytropic power */ \
     if (threadIdx.x < PPOW_N) s_pp[threadIdx.x] = PPOW_TABLE[threadIdx.x]; /* read after the tile's barriers */
 
 // Work item `item` (a tile, or one bin group of a tile) of a stage.
-template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF, bool FUSE, bool PW>
+template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF, bool FUSE, int CT>
 __device__ __forceinline__ void stage_item(const StageArgs &A, const Grid &g, const Phys &ph, const Bins &bins,
                                            int item, TF *__restrict__ s_coef, TF *__restrict__ s_scr,
                                            unsigned char *__restrict__ s_flag, double *__restrict__ s_out,
@@ -542,20 +632,20 @@ __device__ __forceinline__ void stage_item(const StageArgs &A, const Grid &g, co
 {
     const int tile = item / A.ngroups, grp = item - tile * A.ngroups;
     const int b0 = grp * A.bpg, b1 = b0 + A.bpg < bins.nb ? b0 + A.bpg : bins.nb;
-    stage_tile<D, TX_, TY_, TZ_, BLOCK, TF, FUSE, PW>(A, g, ph, bins, tile, b0, b1, grp == 0, s_coef, s_scr, s_flag,
+    stage_tile<D, TX_, TY_, TZ_, BLOCK, TF, FUSE, CT>(A, g, ph, bins, tile, b0, b1, grp == 0, s_coef, s_scr, s_flag,
                                                       s_out, s_pp);
 }
 
-template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF, bool FUSE, bool PW>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((D <= 2 && sizeof(TF) == 4 && !FUSE) ? 5 : 1))) k_stage(StageArgs A, Grid g, Phys ph, Bins bins)
+template <int D, int TX_, int TY_, int TZ_, int BLOCK, typename TF, bool FUSE, int CT>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((D <= 2 && sizeof(TF) == 4 && !FUSE && CT == CT_FIFTHS) ? 5 : 1))) k_stage(StageArgs A, Grid g, Phys ph, Bins bins)
 {
-    BUB_STAGE_SHARED(D, TX_, TY_, TZ_, BLOCK, TF)
+    BUB_STAGE_SHARED(D, TX_, TY_, TZ_, BLOCK, TF, (CT == CT_TRANSFER ? 4 : 2))
     // XCD-aware order: consecutive items land on the same XCD (blocks are dealt round-robin), and
     // the bin groups of a tile are consecutive items, so they share that XCD's L2.
     const int b = blockIdx.x;
     const int item = (b & 7) * A.nblk_per_xcd + (b >> 3);
     if (item >= A.nitems) return;
-    stage_item<D, TX_, TY_, TZ_, BLOCK, TF, FUSE, PW>(A, g, ph, bins, item, s_coef, s_scr, s_flag, s_out, s_pp);
+    stage_item<D, TX_, TY_, TZ_, BLOCK, TF, FUSE, CT>(A, g, ph, bins, item, s_coef, s_scr, s_flag, s_out, s_pp);
 }
 
 }  // namespace bub

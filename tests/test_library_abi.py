@@ -70,9 +70,9 @@ def test_invalid_arguments_rejected_before_device_use(L):
 
 
 def test_ctx_buffer_bytes_host_only(L):
-    """The device footprint of a context is computed on the host: bin table, scalars (with the
-    partial wave-speed maxima, 8 KiB) and the primitive scratch of ndim + 6 fields, each part
-    256-byte aligned."""
+    """The device footprint of a context is computed on the host: bin table (six fields of up to 63
+    bins), scalars (with the partial wave-speed maxima, 8 KiB) and the primitive scratch of ndim + 6
+    fields, each part 256-byte aligned."""
     from paper_2511_21031_amd import _binding as B
     g = B._Grid()
     bn = B._Bins(21, 10e-6, 0.3)
@@ -82,7 +82,7 @@ def test_ctx_buffer_bytes_host_only(L):
     assert L.bub_ctx_buffer_bytes(ctypes.byref(g), ctypes.byref(bn), ctypes.byref(out)) == 0
     n = 70 * 37
     scratch = 8 * (2 + 6) * n
-    assert scratch <= out.value <= scratch + 8 * 3 * 63 + 8192 + 512 + 3 * 256
+    assert scratch <= out.value <= scratch + 8 * 6 * 63 + 8192 + 512 + 3 * 256
     assert out.value % 256 == 0
     assert B.ctx_buffer_bytes(2, (70, 37, 1), 21) == out.value
     g.n[1] = 0

@@ -86,7 +86,7 @@ def test_noalloc_reports_the_error_word_and_rejects_oversized_grids(torch, B, or
     # a clean call afterwards starts from a cleared error word
     rc, _, err = _noalloc(torch, B, case, torch.from_numpy(orc.init_state(pb, case.prim)).cuda())
     assert rc == 0 and err.tolist() == [0, -1, -1]
-    # 724^2 cells need 9984 + 64 * 524176 bytes > 32 MiB: refused before anything is launched
+    # 724^2 cells need 11520 + 64 * 524176 bytes > 32 MiB: refused before anything is launched
     big = W.uniform(2, (724, 724), 1e-4, 3)
     qb = torch.empty((2 + 3 + 6, 1), dtype=torch.float64, device="cuda")
     rc, _, _ = _noalloc(torch, B, big, qb)
