@@ -376,7 +376,9 @@ __global__ void __launch_bounds__(ELT_BLOCK) k_el_stage(ElStageArgs A, ElGrid g,
     constexpr int TX = ELT_X, TY = ELT_Y, TZ = ELT_Z, T = TX * TY * TZ;
     constexpr int FMAX = TX * TY * (TZ + 1) > (TX + 1) * TY * TZ ? TX * TY * (TZ + 1) : (TX + 1) * TY * TZ;
     constexpr int LMAX = TX * TY * (TZ + 6) > (TX + 6) * TY * TZ ? TX * TY * (TZ + 6) : (TX + 6) * TY * TZ;
-    __shared__ double s_f[9][FMAX];    // per face: flux[5], p_L, p_R, u_L, u_R
+    // per face: flux[5], the face pressure (p_L + p_R)/2 and (p_L u_L + p_R u_R)/2; with the line
+    // array 37 KB, so four workgroups (16 waves) fit a CU's LDS
+    __shared__ double s_f[7][FMAX];
     __shared__ double s_l[5][LMAX];    // line array of the current direction: rho, u, v, w, p
     const long long N = g.N;
     const int tid = threadIdx.x;
@@ -427,10 +429,8 @@ __global__ void __launch_bounds__(ELT_BLOCK) k_el_stage(ElStageArgs A, ElGrid g,
             double F[5], pl, pr, ul, ur;
             el_face_flux<d>(st, ph, F, pl, pr, ul, ur);
             for (int k = 0; k < 5; ++k) s_f[k][t] = F[k];
-            s_f[5][t] = pl;
-            s_f[6][t] = pr;
-            s_f[7][t] = ul;
-            s_f[8][t] = ur;
+            s_f[5][t] = 0.5 * (pl + pr);
+            s_f[6][t] = 0.5 * (pl * ul + pr * ur);
         }
         __syncthreads();
         if (active) {
@@ -438,10 +438,8 @@ __global__ void __launch_bounds__(ELT_BLOCK) k_el_stage(ElStageArgs A, ElGrid g,
             const int hi = lo + (d == 0 ? 1 : (d == 1 ? BX : BX * BY));
 #pragma unroll
             for (int k = 0; k < 5; ++k) L[k] += (s_f[k][lo] - s_f[k][hi]) * g.inv_dx;
-            const double pl0 = s_f[5][lo], pr0 = s_f[6][lo], ul0 = s_f[7][lo], ur0 = s_f[8][lo];
-            const double pl1 = s_f[5][hi], pr1 = s_f[6][hi], ul1 = s_f[7][hi], ur1 = s_f[8][hi];
-            gradp[d] = (0.5 * (pl1 + pr1) - 0.5 * (pl0 + pr0)) * g.inv_dx;
-            divpu += (0.5 * (pl1 * ul1 + pr1 * ur1) - 0.5 * (pl0 * ul0 + pr0 * ur0)) * g.inv_dx;
+            gradp[d] = (s_f[5][hi] - s_f[5][lo]) * g.inv_dx;
+            divpu += (s_f[6][hi] - s_f[6][lo]) * g.inv_dx;
         }
         __syncthreads();   // s_l and s_f are rewritten by the next direction
     };
