@@ -272,6 +272,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     ap.add_argument("--workload", choices=["stage", "serving", "collapse3d", "lagrangian"], default="stage")
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="stage: tile shape index to use instead of the autotuner's choice (profiling runs)")
     ap.add_argument("--contents", choices=["polytropic", "transfer"], default="polytropic",
                     help="stage: bubble contents (transfer: gas and vapour with heat and vapour transfer)")
     ap.add_argument("--requests", type=int, default=512)
@@ -388,7 +390,11 @@ def stage_run(bub, torch, case, precision, args) -> dict:
     ctx = bub.context_from_case(case, precision=prec)
     q = ctx.init_state(torch.from_numpy(case.prim).cuda())
     work = ctx.new_work()
-    best, tile_ms = ctx.autotune(q, reps=5)     # project autotuner: fastest stage-kernel tile on this state
+    if args.tile >= 0:
+        ctx.tile = best = args.tile
+        tile_ms = []
+    else:
+        best, tile_ms = ctx.autotune(q, reps=10)    # project autotuner: fastest stage-kernel tile on this state
     ctx.rk3_steps(q, work, args.warmup)
     torch.cuda.synchronize()
     for k in (K_STAGE, K_PRIM, K_OTHER):
