@@ -31,14 +31,6 @@ struct ElGrid {
     long long N;
 };
 
-__device__ inline double el_kernel(double d2, double h)
-{
-    // truncated Gaussian of width h, support d < 3h
-    const double c = 0.063493635934240969;  // (2 pi)^(-3/2)
-    if (d2 >= 9.0 * h * h) return 0.0;
-    return c / (h * h * h) * exp(-0.5 * d2 / (h * h));
-}
-
 // stencil coordinate: periodic wrap, or -1 outside a reflective wall
 __device__ inline int el_wrap(int i, int n, int bc)
 {
@@ -116,6 +108,37 @@ __device__ inline void el_support(const double *b, long long nb, long long i, co
 }
 
 // one wavefront (64 lanes) per bubble
+// Visit the cells of a bubble's kernel support (eq. kernel3D: cut off at distance 3h).  The lanes of the
+// bubble's wavefront take the (x, y) points of the (2m+1)^2 stencil plane (more passes when it exceeds 64)
+// and each walks the 2m+1 z planes of its column, so no lane divides by the stencil width per cell.
+// f(c, e) for every cell c inside the domain and the cut-off, e = exp(-d^2 / (2 h^2)) (the Gaussian
+// without its normalisation).
+template <typename F>
+__device__ __forceinline__ void el_visit(const ElGrid &g, const int host[3], const double xb[3], double h, int m,
+                                         int lane, F &&f)
+{
+    const int w = 2 * m + 1, w2 = w * w;
+    const double cut = 9.0 * h * h, nh = -0.5 / (h * h);
+    const long long nxy = (long long)g.n[0] * g.n[1];
+    for (int p = lane; p < w2; p += 64) {
+        const int ix = host[0] + p % w - m, iy = host[1] + p / w - m;
+        const int cx = el_wrap(ix, g.n[0], g.bc[0]), cy = el_wrap(iy, g.n[1], g.bc[1]);
+        if (cx < 0 || cy < 0) continue;
+        const double ex = (ix + 0.5) * g.dx - xb[0], ey = (iy + 0.5) * g.dx - xb[1];
+        const double dxy = ex * ex + ey * ey;
+        if (!(dxy < cut)) continue;
+        const long long cxy = cx + (long long)g.n[0] * cy;
+        for (int iz = host[2] - m; iz <= host[2] + m; ++iz) {
+            const int cz = el_wrap(iz, g.n[2], g.bc[2]);
+            if (cz < 0) continue;
+            const double ez = (iz + 0.5) * g.dx - xb[2];
+            const double d2 = dxy + ez * ez;
+            if (!(d2 < cut)) continue;
+            f(cxy + nxy * cz, exp(d2 * nh));
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) k_el_gather(const double *__restrict__ P, const double *__restrict__ b,
                                                    long long nb, ElGrid g, Phys ph, double *__restrict__ out)
 {
@@ -127,26 +150,12 @@ __global__ void __launch_bounds__(256) k_el_gather(const double *__restrict__ P,
     double h;
     el_support(b, nb, i, g, host, h, m);
     const double xb[3] = {b[BX_ * nb + i], b[BY_ * nb + i], b[BZ_ * nb + i]};
-    const int w = 2 * m + 1, tot = w * w * w;
+    // normalised weights: the Gaussian's constant factor cancels
     double sw = 0.0, swp = 0.0;
-    for (int o = lane; o < tot; o += 64) {
-        int off[3] = {o % w - m, (o / w) % w - m, o / (w * w) - m};
-        int cc[3];
-        bool out_ = false;
-        double d2 = 0.0;
-        for (int d = 0; d < 3; ++d) {
-            double xc = (host[d] + off[d] + 0.5) * g.dx;
-            d2 += (xc - xb[d]) * (xc - xb[d]);
-            cc[d] = el_wrap(host[d] + off[d], g.n[d], g.bc[d]);
-            if (cc[d] < 0) out_ = true;
-        }
-        if (out_) continue;
-        double wk = el_kernel(d2, h);
-        if (wk == 0.0) continue;
-        long long c = cc[0] + (long long)g.n[0] * (cc[1] + (long long)g.n[1] * cc[2]);
-        sw += wk;
-        swp += wk * P[4 * N + c];
-    }
+    el_visit(g, host, xb, h, m, lane, [&](long long c, double e) {
+        sw += e;
+        swp += e * P[4 * N + c];
+    });
     for (int s = 32; s > 0; s >>= 1) {
         sw += __shfl_xor(sw, s, 64);
         swp += __shfl_xor(swp, s, 64);
@@ -270,26 +279,12 @@ __global__ void __launch_bounds__(256) k_el_scatter(const double *__restrict__ b
     el_support(b, nb, i, g, host, h, m);
     const double xb[3] = {b[BX_ * nb + i], b[BY_ * nb + i], b[BZ_ * nb + i]};
     const double R = b[BRR * nb + i], V = b[BRD * nb + i];
-    const double vol = FOUR_PI_3 * R * R * R, rate = 3.0 * FOUR_PI_3 * R * R * V;
-    const int w = 2 * m + 1, tot = w * w * w;
-    for (int o = lane; o < tot; o += 64) {
-        int off[3] = {o % w - m, (o / w) % w - m, o / (w * w) - m};
-        int cc[3];
-        bool out_ = false;
-        double d2 = 0.0;
-        for (int d = 0; d < 3; ++d) {
-            double xc = (host[d] + off[d] + 0.5) * g.dx;
-            d2 += (xc - xb[d]) * (xc - xb[d]);
-            cc[d] = el_wrap(host[d] + off[d], g.n[d], g.bc[d]);
-            if (cc[d] < 0) out_ = true;
-        }
-        if (out_) continue;
-        double wk = el_kernel(d2, h);
-        if (wk == 0.0) continue;
-        long long c = cc[0] + (long long)g.n[0] * (cc[1] + (long long)g.n[1] * cc[2]);
-        atomicAdd(&aD[c], vol * wk);
-        atomicAdd(&aD[N + c], rate * wk);
-    }
+    const double norm = 0.063493635934240969 / (h * h * h);   // (2 pi)^(-3/2) / h^3
+    const double vol = FOUR_PI_3 * R * R * R * norm, rate = 3.0 * FOUR_PI_3 * R * R * V * norm;
+    el_visit(g, host, xb, h, m, lane, [&](long long c, double e) {
+        atomicAdd(&aD[c], vol * e);
+        atomicAdd(&aD[N + c], rate * e);
+    });
 }
 
 __global__ void k_fill(double *p, long long n, double v)
