@@ -339,3 +339,30 @@ def test_server_results_equal_alone_and_match_oracle(torch, bub, orc, use_run):
         checked += 1
     print(f"requests checked against the oracle: {checked}, worst p/alpha error {worst:.2e}")
     assert checked >= 3
+
+
+def test_batch_mixes_bubble_contents(torch, bub):
+    """Members with polytropic contents and with gas and vapour contents (heat and vapour transfer, four
+    fields per bin), unsplit and split, in one batch run: each ends bitwise equal to its problem stepped
+    alone."""
+    import dataclasses
+    gas = dict(W.AIR, pv=W.PV_WATER_20C)
+    tr = dict(W.AIR_VAPOUR)
+    mem = [("c1", W.c1(), False),
+           ("2d_transfer", dataclasses.replace(W.random_smooth(2, (70, 37), 1e-4, 5, seed=43), gas=gas, contents=tr),
+            False),
+           ("1d_transfer_split", dataclasses.replace(W.c1(n=64, length=64 * 2.5e-4, nb=5, amp_atm=3.0), gas=gas,
+                                                    contents=tr), True)]
+    batch = bub.Batch(bub.PREC_FP64, max_cases=4)
+    held = {}
+    for name, case, split in mem:
+        ctx, q, work = _fresh(torch, bub, case, split, bub.PREC_FP64)
+        batch.add(ctx, q, work, steps=4)
+        held[name] = (ctx, q, work)
+    while batch.run(10):
+        pass
+    torch.cuda.synchronize()
+    for name, case, split in mem:
+        ctx, q, _ = held[name]
+        assert ctx.last_error()[0] == 0, name
+        assert torch.equal(q, _alone(torch, bub, case, split, bub.PREC_FP64, 4)), name
