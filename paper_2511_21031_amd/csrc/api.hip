@@ -926,13 +926,13 @@ int el_smear(bub_ctx *c, const ElGrid &g, const double *b, long long nb, double 
     return hipGetLastError() == hipSuccess ? BUB_OK : BUB_EHIP;
 }
 
-// gather from the primitives in c->d_P, then advance every bubble over (*taup) * scale
-int el_bubbles(bub_ctx *c, const ElGrid &g, double *b, long long nb, double *forcing, const double *taup,
-               double scale, int *nsub, hipStream_t s)
+// gather from the liquid primitives P, then advance every bubble over (*taup) * scale
+int el_bubbles(bub_ctx *c, const ElGrid &g, const double *P, double *b, long long nb, double *forcing,
+               const double *taup, double scale, int *nsub, hipStream_t s)
 {
     if (nb <= 0) return BUB_OK;
     long pr = prof_begin(c, BUB_K_OTHER, s);
-    hipLaunchKernelGGL(k_el_gather, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s, c->d_P, b, nb, g, c->ph, forcing);
+    hipLaunchKernelGGL(k_el_gather, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s, P, b, nb, g, c->ph, forcing);
     ElOdeArgs O{};
     O.b = b;
     O.nb = nb;
@@ -976,7 +976,7 @@ int bub_lagrangian_layout(const bub_ctx *c, int64_t nbub, size_t *work_bytes)
     if (!c || !work_bytes || nbub < 0) return BUB_EINVAL;
     int rc = el_grid(c, &g);
     if (rc) return rc;
-    *work_bytes = sizeof(double) * (size_t)(10 * g.N + 3 * nbub);
+    *work_bytes = sizeof(double) * (size_t)(15 * g.N + 3 * nbub);
     return BUB_OK;
 }
 
@@ -1052,28 +1052,28 @@ int bub_lagrangian_step(bub_ctx *c, double *ql, double *bubbles, int64_t nbub, d
     int rc = el_grid(c, &g);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    double *w1 = work, *w2 = work + 5 * g.N, *forcing = work + 10 * g.N;
+    // work: the two stage results, the bubbles' forcing and a second primitive buffer, which the
+    // stages write for the state they produce (P and P2 take turns, so no stage reads the buffer it
+    // writes)
+    double *w1 = work, *w2 = work + 5 * g.N, *forcing = work + 10 * g.N, *P2 = forcing + 3 * nbub;
     const bool cfl = !(dt > 0.0);
     if ((rc = el_prim(c, g, ql, cfl, s))) return rc;
     hipLaunchKernelGGL(k_dt, dim3(1), dim3(WMAX_SLOTS), 0, s, c->d_sc, cfl ? 0.0 : dt, c->opts.cfl, dt_dev);
     if (nsub && nbub > 0) hipLaunchKernelGGL(k_fill_i, dim3(blocks_for(nbub)), dim3(256), 0, s, nsub, (long long)nbub);
     const double *dtp = &c->d_sc->dt;
-    if ((rc = el_bubbles(c, g, bubbles, nbub, forcing, dtp, 0.5, nsub, s))) return rc;
+    if ((rc = el_bubbles(c, g, c->d_P, bubbles, nbub, forcing, dtp, 0.5, nsub, s))) return rc;
     if ((rc = el_smear(c, g, bubbles, nbub, alpha_D, s))) return rc;
     ElStageArgs A{};
-    A.P = c->d_P;
     A.aD = alpha_D;
     A.dtp = dtp;
-    A.qk = ql; A.qn = nullptr; A.qo = w1; A.a = 0.0; A.b = 1.0;          // P still holds the primitives of ql
+    A.sc = c->d_sc;
+    A.qk = ql; A.qn = nullptr; A.qo = w1; A.a = 0.0; A.b = 1.0; A.P = c->d_P; A.Pout = P2;
     if ((rc = el_stage(c, g, A, s))) return rc;
-    if ((rc = el_prim(c, g, w1, false, s))) return rc;
-    A.qk = w1; A.qn = ql; A.qo = w2; A.a = 0.75; A.b = 0.25;
+    A.qk = w1; A.qn = ql; A.qo = w2; A.a = 0.75; A.b = 0.25; A.P = P2; A.Pout = c->d_P;
     if ((rc = el_stage(c, g, A, s))) return rc;
-    if ((rc = el_prim(c, g, w2, false, s))) return rc;
-    A.qk = w2; A.qn = ql; A.qo = ql; A.a = 1.0 / 3.0; A.b = 2.0 / 3.0;
+    A.qk = w2; A.qn = ql; A.qo = ql; A.a = 1.0 / 3.0; A.b = 2.0 / 3.0; A.P = c->d_P; A.Pout = P2;
     if ((rc = el_stage(c, g, A, s))) return rc;
-    if ((rc = el_prim(c, g, ql, false, s))) return rc;
-    if ((rc = el_bubbles(c, g, bubbles, nbub, forcing, dtp, 0.5, nsub, s))) return rc;
+    if ((rc = el_bubbles(c, g, P2, bubbles, nbub, forcing, dtp, 0.5, nsub, s))) return rc;
     return el_smear(c, g, bubbles, nbub, alpha_D, s);
 }
 

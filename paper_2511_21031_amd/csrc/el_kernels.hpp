@@ -301,6 +301,10 @@ struct ElStageArgs {
     const double *dtp;
     double a, b;
     int rhs_mode;
+    // RK mode: the epilogue also writes the primitives of the state it produces (the arithmetic of
+    // k_el_prim) into Pout, which must not be P; null: the next stage needs a primitive pass.
+    double *Pout;
+    Scalars *sc;          // error word (with Pout)
 };
 
 // Liquid face between cell (c - e_d) and c from its six-cell stencil st[o][v] (cells c - 3 + o along d,
@@ -448,14 +452,28 @@ __global__ void __launch_bounds__(ELT_BLOCK) k_el_stage(ElStageArgs A, ElGrid g,
     L[0] += rho * D * ioma;
     for (int d = 0; d < 3; ++d) L[1 + d] += rho * A.P[(1 + d) * N + c] * D * ioma - a * gradp[d] * ioma;
     L[4] += E * D * ioma - a * divpu * ioma;
+    double out[5];
     for (int k = 0; k < 5; ++k) {
         long long o = (long long)k * N + c;
-        if (A.rhs_mode) A.qo[o] = L[k];
+        if (A.rhs_mode) out[k] = L[k];
         else {
-            double r = A.b * (A.qk[o] + dt * L[k]);
-            if (A.a != 0.0) r += A.a * A.qn[o];
-            A.qo[o] = r;
+            out[k] = A.b * (A.qk[o] + dt * L[k]);
+            if (A.a != 0.0) out[k] += A.a * A.qn[o];
         }
+        A.qo[o] = out[k];
+    }
+    if (A.Pout) {
+        const double rn = out[0], irn = frcp(rn);
+        double un[3], ke = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            un[d] = out[1 + d] * irn;
+            ke += un[d] * un[d];
+        }
+        const double pn = ph.gm1 * (out[4] - 0.5 * rn * ke) - ph.gpi;
+        A.Pout[c] = rn;
+        for (int d = 0; d < 3; ++d) A.Pout[(1 + d) * N + c] = un[d];
+        A.Pout[4 * N + c] = pn;
+        if (!(rn > 0.0) || !(pn + ph.pi_inf > 0.0)) raise_error(A.sc, E_NONFINITE, c, -1);
     }
 }
 
