@@ -299,8 +299,9 @@ def test_bin_groups_give_identical_results(torch, bub, orc, kind, prec):
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("shape", [(1024, 512, 1), (84, 84, 84)])
 def test_fused_primitive_pass_is_bitwise_the_separate_pass(torch, bub, orc, shape, prec):
-    """From 2^19 cells on, stages 1 and 2 write the next stage's primitives from their epilogue; two
-    workgroups per tile (forced) take the separate primitive pass instead.  Same arithmetic, same bin
+    """From 2^19 cells on, stages 1 and 2 write the next stage's primitives from their epilogue (not in
+    3D FP64, which always takes the separate pass); two workgroups per tile (forced) take the
+    separate primitive pass instead.  Same arithmetic, same bin
     order: the steps must agree bit for bit (right-hand sides and states)."""
     ndim = 2 if shape[2] == 1 else 3
     n = shape[:ndim]

@@ -53,8 +53,11 @@ def _check_forcing(pb, f, f_ref):
 
 
 @pytest.mark.parametrize("bc", [0, 1])
-def test_smear_and_gather(torch, bub, orc, bc):
-    lc, pb, ctx = _setup(orc, bub, bc=bc)
+@pytest.mark.parametrize("n", [16, 8, 18])
+def test_smear_and_gather(torch, bub, orc, bc, n):
+    """Grids of 16, 8 and 18 cells a side: on the smaller ones the wide supports wrap around the
+    periodic box more often, or lie further outside the reflective one."""
+    lc, pb, ctx = _setup(orc, bub, n=n, bc=bc)
     bub_h = orc.el_bubbles(pb, lc.bubbles[:3], lc.bubbles[3])
     bub_h[4] *= np.linspace(0.9, 1.3, lc.nbub)
     bub_h[5] = np.linspace(-2, 2, lc.nbub)
