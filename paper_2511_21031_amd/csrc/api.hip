@@ -126,7 +126,8 @@ void tile_info(int *tx, int *ty, int *tz, int *block)
 // The kernels are compiled for the bubble contents (Contents): polytropic gas whose power x^(3 kappa)
 // takes the fifth-root Newton form when 3 kappa is a whole number of fifths (air's 4.2, 3, 5, ...) or the
 // general exp2(3 kappa log2 x) form otherwise, or transfer contents.  Only the fifth-root form has every
-// stage shape and the fused epilogue; the others run stage shape 0 with the separate primitive pass.
+// stage shape; the others run stage shape 0, transfer contents with the fused epilogue where it applies,
+// the general power with the separate primitive pass.
 int ct_of(const bub_ctx *c)
 {
     if (c->opts.contents == BUB_CONTENTS_TRANSFER) return CT_TRANSFER;
@@ -208,9 +209,13 @@ int launch_stage_t(bub_ctx *c, StageArgs A, hipStream_t s)
     const dim3 grid(8 * A.nblk_per_xcd), block(TC::BLOCK);
     if (!pw_fast(c)) {
         if constexpr (V == 0) {
-            if (A.Pout) return BUB_EINVAL;   // (stage_fusable is false for these contents)
+            const bool tr = ct_of(c) == CT_TRANSFER;
+            if (A.Pout && !tr) return BUB_EINVAL;   // (stage_fusable is false for the general power)
             long pr = prof_begin(c, BUB_K_STAGE, s);
-            if (ct_of(c) == CT_TRANSFER)
+            if (tr && A.Pout)
+                hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF, true, CT_TRANSFER>), grid,
+                                   block, 0, s, A, c->g, c->ph, c->bt);
+            else if (tr)
                 hipLaunchKernelGGL((k_stage<D, TC::TX, TC::TY, TC::TZ, TC::BLOCK, TF, false, CT_TRANSFER>), grid,
                                    block, 0, s, A, c->g, c->ph, c->bt);
             else
@@ -405,7 +410,7 @@ long long stage_tiles(const bub_ctx *c)
 bool stage_fusable(const bub_ctx *c)
 {
     // (a viscous or source pass after the stage changes the state the epilogue would describe)
-    if (!c->d_P2 || slots_for(c->N) != 1 || c->opts.viscous || c->src_on || !pw_fast(c)) return false;
+    if (!c->d_P2 || slots_for(c->N) != 1 || c->opts.viscous || c->src_on || ct_of(c) == CT_POLY) return false;
     // 3D FP64: the epilogue's registers cost the stage more than the pass it saves (measured at 256^3
     // x 21 bins: 13.6 ms fused against 11.9 + 1.5 ms)
     if (c->ndim == 3 && c->opts.precision == BUB_PREC_FP64) return false;

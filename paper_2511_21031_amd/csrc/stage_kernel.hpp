@@ -151,7 +151,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
     constexpr int T = G::T, F = G::F, C = G::C, NC = G::NC, NCF = G::NCF, L = G::L;
     constexpr bool TR = CT == CT_TRANSFER;   // transfer contents: n p_b and n m_v per bin as well
     constexpr bool PW = CT == CT_FIFTHS;
-    static_assert(!(TR && FUSE), "the fused epilogue takes polytropic contents");
     constexpr int CPT = (C + BLOCK - 1) / BLOCK;  // cross cells staged per thread
     const int tx = tile % A.ntile[0];
     const int ty = (tile / A.ntile[0]) % A.ntile[1];
@@ -579,7 +578,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs &A, const Grid &g, co
                 A.qo[(long long)(iNP + ib) * N + gc] = xp;
                 A.qo[(long long)(iNM + ib) * N + gc] = xm;
             }
-            if constexpr (fuse) bin_add<PW>(acc, ib, xr, xv, bins.w[ib], pg0, r0, nb, ph, s_pp);
+            if constexpr (fuse) {
+                if constexpr (TR) bin_add_tr(acc, ib, xr, xv, xp, bins.w[ib], nb);
+                else bin_add<PW>(acc, ib, xr, xv, bins.w[ib], pg0, r0, nb, ph, s_pp);
+            }
             if constexpr (DEFER) {
                 s_out[tid] = xr;
                 s_out[BLOCK + tid] = xv;

@@ -105,8 +105,8 @@ def test_unsplit_trajectory(torch, bub, orc, kind):
     assert np.all(err <= np.maximum(1e-10, 10 * env))
 
 
-def test_fused_size_takes_the_separate_pass(torch, bub, orc):
-    """1024 x 512 (where polytropic air fuses the primitive pass into the stages): 2 RK3 steps."""
+def test_fused_size_steps(torch, bub, orc):
+    """1024 x 512, where the stages carry the primitive pass of the state they write: 2 RK3 steps."""
     case = _transfer(W.random_smooth(2, (1024, 512), 1e-4, 3, seed=55))
     pb = orc.problem_from_case(case)
     qh = _off_equilibrium(orc, pb, case, seed=5)
@@ -123,6 +123,29 @@ def test_fused_size_takes_the_separate_pass(torch, bub, orc):
     err, env = rel_err(q.cpu().numpy(), q_ref), rel_err(q_pert, q_ref)
     print(f"1024x512 transfer, 2 steps: max field err {err.max():.3e} (drift {env.max():.3e})")
     assert np.all(err <= np.maximum(1e-10, 10 * env))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fused_primitive_pass_is_bitwise_the_separate_pass(torch, bub, orc, prec):
+    """1024 x 512 x 5 bins: the stages' epilogue writes the next stage's primitives (n p_b summed in bin
+    order as the primitive pass does); two workgroups per tile (forced) take the separate pass.  The
+    unsplit steps must agree bit for bit."""
+    case = _transfer(W.random_smooth(2, (1024, 512), 1e-4, 5, seed=57))
+    pb = orc.problem_from_case(case)
+    q0 = _gpu(torch, _off_equilibrium(orc, pb, case, seed=8))
+    P = bub.PREC_FP64 if prec == "fp64" else bub.PREC_MIXED
+    outs = []
+    for groups in (0, 2):
+        ctx = bub.context_from_case(case, precision=P)
+        ctx.set_bin_groups(groups)
+        q = q0.clone()
+        work = ctx.new_work()
+        for _ in range(2):
+            ctx.rk3_step(q, work)
+        assert ctx.last_error()[0] == 0
+        outs.append(q.cpu().numpy())
+        del ctx, work
+    assert np.array_equal(outs[0], outs[1])
 
 
 @pytest.mark.parametrize("ndim", [1, 3])
