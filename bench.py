@@ -247,8 +247,7 @@ def lagrangian(args, quiet=False):
         ctx.lagrangian_step(ql, bg, aD, work)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.lagrangian_step(ql, bg, aD, work)
+    ctx.lagrangian_steps(ql, bg, aD, work, args.steps)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     code = ctx.last_error()[0]

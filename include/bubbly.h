@@ -317,6 +317,16 @@ int bub_lagrangian_rhs(bub_ctx *ctx, const double *ql, const double *alpha_D, do
 int bub_lagrangian_step(bub_ctx *ctx, double *ql, double *bubbles, int64_t nbub, double *alpha_D, double *work,
                         double dt, double *dt_dev, int32_t *nsub, void *stream);
 
+/* nsteps Lagrangian steps in one call (same arguments; dt_dev receives the
+ * last step's dt, nsub the last step's sub-step counts).  A step's closing
+ * smear is overwritten by the next step's smear before anything reads it (the
+ * bubbles' half-step gathers the liquid alone), so only the last step makes
+ * it: ql and the bubbles are those of nsteps separate calls, up to the order
+ * of the smears' atomic adds.  BUB_EINVAL for nsteps < 0 or the argument
+ * errors of bub_lagrangian_step. */
+int bub_lagrangian_steps(bub_ctx *ctx, double *ql, double *bubbles, int64_t nbub, double *alpha_D, double *work,
+                         int nsteps, double dt, double *dt_dev, int32_t *nsub, void *stream);
+
 /* ---- Batches: many resident problems advanced together ----
  * A batch holds up to max_cases problems (contexts of any dimensionality, bin
  * count, size and bubble mode, all of the batch's precision) with their state q

@@ -93,6 +93,7 @@ _SIGS = {
     "bub_lagrangian_gather": [_vp, _vp, _vp, _i64, _vp, _vp],
     "bub_lagrangian_rhs": [_vp, _vp, _vp, _vp, _vp],
     "bub_lagrangian_step": [_vp, _vp, _vp, _i64, _vp, _vp, ctypes.c_double, _vp, _vp, _vp],
+    "bub_lagrangian_steps": [_vp, _vp, _vp, _i64, _vp, _vp, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp],
     "bub_tile_count": [_vp, ctypes.POINTER(ctypes.c_int)],
     "bub_tile_info": [_vp, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4,
     "bub_tile_set": [_vp, ctypes.c_int],
@@ -361,6 +362,13 @@ class Context:
                                          _ptr(work), float(dt), _ptr(dt_dev),
                                          None if nsub is None else _vp(nsub.data_ptr()), _stream(stream)),
                "bub_lagrangian_step")
+
+    def lagrangian_steps(self, ql, bubbles, alpha_D, work, nsteps, dt=0.0, dt_dev=None, nsub=None, stream=None):
+        """nsteps Lagrangian steps in one call (only the last one's closing smear is made)."""
+        _check(lib().bub_lagrangian_steps(self._h, _ptr(ql), _ptr(bubbles), bubbles.shape[1], _ptr(alpha_D),
+                                          _ptr(work), int(nsteps), float(dt), _ptr(dt_dev),
+                                          None if nsub is None else _vp(nsub.data_ptr()), _stream(stream)),
+               "bub_lagrangian_steps")
 
     def tiles(self):
         """List of (tx, ty, tz, block) stage-kernel tile shapes for this dimensionality."""

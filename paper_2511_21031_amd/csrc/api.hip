@@ -1054,8 +1054,14 @@ int bub_lagrangian_rhs(bub_ctx *c, const double *ql, const double *alpha_D, doub
 int bub_lagrangian_step(bub_ctx *c, double *ql, double *bubbles, int64_t nbub, double *alpha_D, double *work,
                         double dt, double *dt_dev, int32_t *nsub, void *stream)
 {
+    return bub_lagrangian_steps(c, ql, bubbles, nbub, alpha_D, work, 1, dt, dt_dev, nsub, stream);
+}
+
+int bub_lagrangian_steps(bub_ctx *c, double *ql, double *bubbles, int64_t nbub, double *alpha_D, double *work,
+                         int nsteps, double dt, double *dt_dev, int32_t *nsub, void *stream)
+{
     ElGrid g;
-    if (!c || !ql || !alpha_D || !work || nbub < 0 || (nbub > 0 && !bubbles)) return BUB_EINVAL;
+    if (!c || !ql || !alpha_D || !work || nbub < 0 || nsteps < 0 || (nbub > 0 && !bubbles)) return BUB_EINVAL;
     if (!(dt == dt) || dt == INFINITY) return BUB_EINVAL;
     int rc = el_grid(c, &g);
     if (rc) return rc;
@@ -1065,24 +1071,30 @@ int bub_lagrangian_step(bub_ctx *c, double *ql, double *bubbles, int64_t nbub, d
     // writes)
     double *w1 = work, *w2 = work + 5 * g.N, *forcing = work + 10 * g.N, *P2 = forcing + 3 * nbub;
     const bool cfl = !(dt > 0.0);
-    if ((rc = el_prim(c, g, ql, cfl, s))) return rc;
-    hipLaunchKernelGGL(k_dt, dim3(1), dim3(WMAX_SLOTS), 0, s, c->d_sc, cfl ? 0.0 : dt, c->opts.cfl, dt_dev);
-    if (nsub && nbub > 0) hipLaunchKernelGGL(k_fill_i, dim3(blocks_for(nbub)), dim3(256), 0, s, nsub, (long long)nbub);
     const double *dtp = &c->d_sc->dt;
-    if ((rc = el_bubbles(c, g, c->d_P, bubbles, nbub, forcing, dtp, 0.5, nsub, s))) return rc;
-    if ((rc = el_smear(c, g, bubbles, nbub, alpha_D, s))) return rc;
-    ElStageArgs A{};
-    A.aD = alpha_D;
-    A.dtp = dtp;
-    A.sc = c->d_sc;
-    A.qk = ql; A.qn = nullptr; A.qo = w1; A.a = 0.0; A.b = 1.0; A.P = c->d_P; A.Pout = P2;
-    if ((rc = el_stage(c, g, A, s))) return rc;
-    A.qk = w1; A.qn = ql; A.qo = w2; A.a = 0.75; A.b = 0.25; A.P = P2; A.Pout = c->d_P;
-    if ((rc = el_stage(c, g, A, s))) return rc;
-    A.qk = w2; A.qn = ql; A.qo = ql; A.a = 1.0 / 3.0; A.b = 2.0 / 3.0; A.P = c->d_P; A.Pout = P2;
-    if ((rc = el_stage(c, g, A, s))) return rc;
-    if ((rc = el_bubbles(c, g, P2, bubbles, nbub, forcing, dtp, 0.5, nsub, s))) return rc;
-    return el_smear(c, g, bubbles, nbub, alpha_D, s);
+    for (int k = 0; k < nsteps; ++k) {
+        if ((rc = el_prim(c, g, ql, cfl, s))) return rc;
+        hipLaunchKernelGGL(k_dt, dim3(1), dim3(WMAX_SLOTS), 0, s, c->d_sc, cfl ? 0.0 : dt, c->opts.cfl, dt_dev);
+        if (nsub && nbub > 0)
+            hipLaunchKernelGGL(k_fill_i, dim3(blocks_for(nbub)), dim3(256), 0, s, nsub, (long long)nbub);
+        if ((rc = el_bubbles(c, g, c->d_P, bubbles, nbub, forcing, dtp, 0.5, nsub, s))) return rc;
+        if ((rc = el_smear(c, g, bubbles, nbub, alpha_D, s))) return rc;
+        ElStageArgs A{};
+        A.aD = alpha_D;
+        A.dtp = dtp;
+        A.sc = c->d_sc;
+        A.qk = ql; A.qn = nullptr; A.qo = w1; A.a = 0.0; A.b = 1.0; A.P = c->d_P; A.Pout = P2;
+        if ((rc = el_stage(c, g, A, s))) return rc;
+        A.qk = w1; A.qn = ql; A.qo = w2; A.a = 0.75; A.b = 0.25; A.P = P2; A.Pout = c->d_P;
+        if ((rc = el_stage(c, g, A, s))) return rc;
+        A.qk = w2; A.qn = ql; A.qo = ql; A.a = 1.0 / 3.0; A.b = 2.0 / 3.0; A.P = c->d_P; A.Pout = P2;
+        if ((rc = el_stage(c, g, A, s))) return rc;
+        if ((rc = el_bubbles(c, g, P2, bubbles, nbub, forcing, dtp, 0.5, nsub, s))) return rc;
+        // the closing smear of a step is read by nothing before the next step smears again (its bubble
+        // half-step gathers the liquid only), so only the last step's is made
+        if (k == nsteps - 1 && (rc = el_smear(c, g, bubbles, nbub, alpha_D, s))) return rc;
+    }
+    return BUB_OK;
 }
 
 int bub_bubble_advance(bub_ctx *c, double *q, double tau, int32_t *nsub, void *stream)

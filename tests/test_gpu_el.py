@@ -120,6 +120,43 @@ def test_step_trajectory(torch, bub, orc):
     assert rel_err(aD.cpu().numpy()[0], a_ref) < tol
 
 
+def test_multi_step_call(torch, bub, orc):
+    """lagrangian_steps(10), which makes only the last step's closing smear, against ten single-step calls
+    and ten oracle steps, all with the CFL step size; zero steps change nothing."""
+    lc, pb, ctx = _setup(orc, bub, n=16, nbub=80)
+    ql0 = orc.el_liquid_state(pb, lc.prim)
+    b0 = orc.el_bubbles(pb, lc.bubbles[:3], lc.bubbles[3])
+    b0[4] *= np.linspace(0.9, 1.2, lc.nbub)     # away from equilibrium
+    ql_ref, b_ref = ql0.copy(), b0.copy()
+    a_ref, d_ref = orc.el_smear(pb, b_ref)
+    for _ in range(10):
+        orc.el_step(pb, ql_ref, b_ref, a_ref, d_ref)
+    runs = []
+    for multi in (True, False):
+        ql, bg = _gpu(torch, ql0), _gpu(torch, b0)
+        aD = ctx.lagrangian_smear(bg)
+        work = ctx.lagrangian_work(lc.nbub)
+        if multi:
+            before = ql.clone()
+            ctx.lagrangian_steps(ql, bg, aD, work, 0)
+            assert torch.equal(ql, before)
+            ctx.lagrangian_steps(ql, bg, aD, work, 10)
+        else:
+            for _ in range(10):
+                ctx.lagrangian_step(ql, bg, aD, work)
+        assert ctx.last_error()[0] == 0
+        runs.append((ql.cpu().numpy(), bg.cpu().numpy(), aD.cpu().numpy()))
+    (qm, bm, am), (qs, bs, as_) = runs
+    print("multi vs single: ql", rel_err(qm, qs).max(), "R", rel_err(bm[4], bs[4]),
+          "; multi vs oracle: ql", rel_err(qm, ql_ref).max(), "R", rel_err(bm[4], b_ref[4]))
+    tol = 10 * RTOL   # the smears' atomic order may move a bubble's sub-step count
+    for q, b, a in runs:
+        assert rel_err(q, ql_ref).max() < tol
+        assert rel_err(b[4], b_ref[4]) < tol and rel_err(b[5], b_ref[5]) < tol
+        assert rel_err(a[0], a_ref) < tol and rel_err(a[1], d_ref) < tol
+    assert rel_err(qm, qs).max() < tol and rel_err(bm[4], bs[4]) < tol
+
+
 def test_full_size_smear_gather_and_steps(torch, bub, orc):
     """192^3 with 1e5 bubbles: full smear and gather against the oracle, then two whole steps on the GPU."""
     lc = W.c4()
