@@ -322,8 +322,10 @@ int bub_lagrangian_step(bub_ctx *ctx, double *ql, double *bubbles, int64_t nbub,
  * smear is overwritten by the next step's smear before anything reads it (the
  * bubbles' half-step gathers the liquid alone), so only the last step makes
  * it: ql and the bubbles are those of nsteps separate calls, up to the order
- * of the smears' atomic adds.  BUB_EINVAL for nsteps < 0 or the argument
- * errors of bub_lagrangian_step. */
+ * of the smears' atomic adds.  The last liquid stage of each step but the
+ * final one also computes the primitives and wave speeds of the state it
+ * writes, so later steps start without a primitive pass of their own.
+ * BUB_EINVAL for nsteps < 0 or the argument errors of bub_lagrangian_step. */
 int bub_lagrangian_steps(bub_ctx *ctx, double *ql, double *bubbles, int64_t nbub, double *alpha_D, double *work,
                          int nsteps, double dt, double *dt_dev, int32_t *nsub, void *stream);
 

@@ -1066,33 +1066,37 @@ int bub_lagrangian_steps(bub_ctx *c, double *ql, double *bubbles, int64_t nbub, 
     int rc = el_grid(c, &g);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    // work: the two stage results, the bubbles' forcing and a second primitive buffer, which the
-    // stages write for the state they produce (P and P2 take turns, so no stage reads the buffer it
-    // writes)
-    double *w1 = work, *w2 = work + 5 * g.N, *forcing = work + 10 * g.N, *P2 = forcing + 3 * nbub;
+    // work: the two stage results, the bubbles' forcing and a second primitive buffer.  The stages
+    // write the primitives of the state they produce into the buffer they do not read (Pc and Po
+    // take turns); the last stage of a step that another step follows also posts that state's wave
+    // speeds, so the next step starts from Pc without a primitive pass of its own.
+    double *w1 = work, *w2 = work + 5 * g.N, *forcing = work + 10 * g.N;
+    double *Pc = c->d_P, *Po = forcing + 3 * nbub;
     const bool cfl = !(dt > 0.0);
     const double *dtp = &c->d_sc->dt;
     for (int k = 0; k < nsteps; ++k) {
-        if ((rc = el_prim(c, g, ql, cfl, s))) return rc;
+        if (k == 0 && (rc = el_prim(c, g, ql, cfl, s))) return rc;
         hipLaunchKernelGGL(k_dt, dim3(1), dim3(WMAX_SLOTS), 0, s, c->d_sc, cfl ? 0.0 : dt, c->opts.cfl, dt_dev);
         if (nsub && nbub > 0)
             hipLaunchKernelGGL(k_fill_i, dim3(blocks_for(nbub)), dim3(256), 0, s, nsub, (long long)nbub);
-        if ((rc = el_bubbles(c, g, c->d_P, bubbles, nbub, forcing, dtp, 0.5, nsub, s))) return rc;
+        if ((rc = el_bubbles(c, g, Pc, bubbles, nbub, forcing, dtp, 0.5, nsub, s))) return rc;
         if ((rc = el_smear(c, g, bubbles, nbub, alpha_D, s))) return rc;
         ElStageArgs A{};
         A.aD = alpha_D;
         A.dtp = dtp;
         A.sc = c->d_sc;
-        A.qk = ql; A.qn = nullptr; A.qo = w1; A.a = 0.0; A.b = 1.0; A.P = c->d_P; A.Pout = P2;
+        A.qk = ql; A.qn = nullptr; A.qo = w1; A.a = 0.0; A.b = 1.0; A.P = Pc; A.Pout = Po;
         if ((rc = el_stage(c, g, A, s))) return rc;
-        A.qk = w1; A.qn = ql; A.qo = w2; A.a = 0.75; A.b = 0.25; A.P = P2; A.Pout = c->d_P;
+        A.qk = w1; A.qn = ql; A.qo = w2; A.a = 0.75; A.b = 0.25; A.P = Po; A.Pout = Pc;
         if ((rc = el_stage(c, g, A, s))) return rc;
-        A.qk = w2; A.qn = ql; A.qo = ql; A.a = 1.0 / 3.0; A.b = 2.0 / 3.0; A.P = c->d_P; A.Pout = P2;
+        A.qk = w2; A.qn = ql; A.qo = ql; A.a = 1.0 / 3.0; A.b = 2.0 / 3.0; A.P = Pc; A.Pout = Po;
+        A.cfl = cfl && k + 1 < nsteps;
         if ((rc = el_stage(c, g, A, s))) return rc;
-        if ((rc = el_bubbles(c, g, P2, bubbles, nbub, forcing, dtp, 0.5, nsub, s))) return rc;
+        if ((rc = el_bubbles(c, g, Po, bubbles, nbub, forcing, dtp, 0.5, nsub, s))) return rc;
         // the closing smear of a step is read by nothing before the next step smears again (its bubble
         // half-step gathers the liquid only), so only the last step's is made
         if (k == nsteps - 1 && (rc = el_smear(c, g, bubbles, nbub, alpha_D, s))) return rc;
+        std::swap(Pc, Po);
     }
     return BUB_OK;
 }

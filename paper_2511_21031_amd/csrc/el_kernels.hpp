@@ -305,6 +305,7 @@ struct ElStageArgs {
     // k_el_prim) into Pout, which must not be P; null: the next stage needs a primitive pass.
     double *Pout;
     Scalars *sc;          // error word (with Pout)
+    int cfl;              // with Pout: also post the wave-speed maxima of the written state (k_el_prim<true>)
 };
 
 // Liquid face between cell (c - e_d) and c from its six-cell stencil st[o][v] (cells c - 3 + o along d,
@@ -445,36 +446,43 @@ __global__ void __launch_bounds__(ELT_BLOCK) k_el_stage(ElStageArgs A, ElGrid g,
     dir(std::integral_constant<int, 0>{});
     dir(std::integral_constant<int, 1>{});
     dir(std::integral_constant<int, 2>{});
-    if (!active) return;
-    double rho = A.P[c], E = A.qk[4 * N + c];
-    double a = A.aD[c], D = A.aD[N + c];
-    double ioma = 1.0 / (1.0 - a);
-    L[0] += rho * D * ioma;
-    for (int d = 0; d < 3; ++d) L[1 + d] += rho * A.P[(1 + d) * N + c] * D * ioma - a * gradp[d] * ioma;
-    L[4] += E * D * ioma - a * divpu * ioma;
-    double out[5];
-    for (int k = 0; k < 5; ++k) {
-        long long o = (long long)k * N + c;
-        if (A.rhs_mode) out[k] = L[k];
-        else {
-            out[k] = A.b * (A.qk[o] + dt * L[k]);
-            if (A.a != 0.0) out[k] += A.a * A.qn[o];
+    double wcfl = 0.0;   // inactive lanes stay in the wave for the maxima's reduction
+    if (active) {
+        double rho = A.P[c], E = A.qk[4 * N + c];
+        double a = A.aD[c], D = A.aD[N + c];
+        double ioma = 1.0 / (1.0 - a);
+        L[0] += rho * D * ioma;
+        for (int d = 0; d < 3; ++d) L[1 + d] += rho * A.P[(1 + d) * N + c] * D * ioma - a * gradp[d] * ioma;
+        L[4] += E * D * ioma - a * divpu * ioma;
+        double out[5];
+        for (int k = 0; k < 5; ++k) {
+            long long o = (long long)k * N + c;
+            if (A.rhs_mode) out[k] = L[k];
+            else {
+                out[k] = A.b * (A.qk[o] + dt * L[k]);
+                if (A.a != 0.0) out[k] += A.a * A.qn[o];
+            }
+            A.qo[o] = out[k];
         }
-        A.qo[o] = out[k];
-    }
-    if (A.Pout) {
-        const double rn = out[0], irn = frcp(rn);
-        double un[3], ke = 0.0;
-        for (int d = 0; d < 3; ++d) {
-            un[d] = out[1 + d] * irn;
-            ke += un[d] * un[d];
+        if (A.Pout) {
+            const double rn = out[0], irn = frcp(rn);
+            double un[3], ke = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                un[d] = out[1 + d] * irn;
+                ke += un[d] * un[d];
+            }
+            const double pn = ph.gm1 * (out[4] - 0.5 * rn * ke) - ph.gpi;
+            A.Pout[c] = rn;
+            for (int d = 0; d < 3; ++d) A.Pout[(1 + d) * N + c] = un[d];
+            A.Pout[4 * N + c] = pn;
+            if (!(rn > 0.0) || !(pn + ph.pi_inf > 0.0)) raise_error(A.sc, E_NONFINITE, c, -1);
+            if (A.cfl) {
+                const double cs = sqrt(ph.gamma * (pn + ph.pi_inf) * irn);
+                for (int d = 0; d < 3; ++d) wcfl = dmax(wcfl, (fabs(un[d]) + cs) * g.inv_dx);
+            }
         }
-        const double pn = ph.gm1 * (out[4] - 0.5 * rn * ke) - ph.gpi;
-        A.Pout[c] = rn;
-        for (int d = 0; d < 3; ++d) A.Pout[(1 + d) * N + c] = un[d];
-        A.Pout[4 * N + c] = pn;
-        if (!(rn > 0.0) || !(pn + ph.pi_inf > 0.0)) raise_error(A.sc, E_NONFINITE, c, -1);
     }
+    if (A.cfl) wmax_post(wcfl, A.sc);
 }
 
 }  // namespace bub
