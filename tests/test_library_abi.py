@@ -67,6 +67,8 @@ def test_invalid_arguments_rejected_before_device_use(L):
     assert L.bub_ctx_create(None, None, None, None, None, None) == -1
     assert L.bub_rk3_step(None, None, None, 0.0, None, None) == -1
     assert L.bub_layout(None, None, None, None, None, None) == -1
+    assert L.bub_lagrangian_step(None, None, None, 0, None, None, 0.0, None, None, None) == -1
+    assert L.bub_lagrangian_steps(None, None, None, 0, None, None, 3, 0.0, None, None, None) == -1
 
 
 def test_ctx_buffer_bytes_host_only(L):
